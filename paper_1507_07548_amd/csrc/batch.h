@@ -1,0 +1,69 @@
+// Host-side objects behind the opaque ms2_ctx / ms2_batch handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+namespace ms2 {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need);
+  void release();
+};
+
+struct TileCfg {
+  int waves = 1;    // waves per block (64 i molecules each)
+  int jchunk = 64;  // j molecules per work item
+};
+
+struct CachedItems {
+  DevBuf buf;
+  int count = 0;
+  int jsplits = 0;
+};
+
+constexpr int kRing = 32;
+struct RingSlot {
+  SlotDev* h_slot = nullptr;
+  SysParams* h_prm = nullptr;
+  SlotDev* d_slot = nullptr;
+  SysParams* d_prm = nullptr;
+  hipEvent_t ev = nullptr;
+  bool used = false;
+};
+
+ms2_status set_error(ms2_status s, const std::string& msg);
+ms2_status hip_status(hipError_t e, const char* where);
+
+}  // namespace ms2
+
+struct ms2_ctx {
+  int device = 0;
+  int cls = 0;
+  ms2::SpeciesTable tab;
+  ms2::SpeciesTable* d_tab = nullptr;
+  // scratch of the single-system entry points
+  ms2::DevBuf s_sites, s_pf, s_bsum, s_skp, s_sk, s_fk, s_kred, s_ksum;
+  std::map<int, std::pair<ms2::DevBuf, int>> kvecs;            // kmax2 -> (table, count)
+  std::map<std::tuple<int, int, int>, ms2::CachedItems> item_cache;
+  std::map<std::tuple<int, int, int>, ms2::TileCfg> tuned;     // (mode, precision, n) -> shape
+  ms2::RingSlot ring[ms2::kRing];
+  int ring_pos = 0;
+};
+
+namespace ms2 {
+ms2_status check_params(const ms2_ctx* ctx, const ms2_params* p);
+void build_sys_params(const ms2_ctx* ctx, const ms2_params* p, int nk, SysParams& s);
+ms2_status kvec_table(ms2_ctx* ctx, int kmax2, const KVec** d_out, int* nk);
+TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n);
+void build_items(int n, const TileCfg& c, int slot, int item0, std::vector<WorkItem>& out,
+                 int* jsplits);
+}  // namespace ms2

@@ -1,0 +1,115 @@
+// Internal layout of the MI355X force/energy path: device tables, per-system
+// parameters, per-slot buffer descriptors and pair-kernel work items.
+// Shared by the HIP kernels and the host side of the C ABI only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ms2.h"
+
+namespace ms2 {
+
+// Half-space integer k vectors: n_x > 0, or n_x == 0 and n_y > 0, or
+// n_x == n_y == 0 and n_z > 0, with 0 < |n|^2 <= kmax2.
+struct KVec { int nx, ny, nz, n2; };
+
+constexpr int kMaxSp = MS2_MAX_SPECIES;
+constexpr int kMaxS = MS2_MAX_SITES;
+constexpr int kNumBlockSums = 6;  // u_lj, u_el, us, uss, npair, nsite per work item
+constexpr int kKChunk = 128;      // k vectors per reciprocal-force block
+constexpr int kMolTile = 64;      // molecules per structure-factor block
+constexpr int kMaxRdfTypes = 16;
+
+// Model classes: compile-time upper bounds on the sites of each type per
+// molecule.  Each class is one instantiation of the pair kernel; a system
+// runs in the smallest class that covers every species it uses.
+struct ClassShape { int lj, ch, dp, qd; };
+constexpr int kNumClasses = 6;
+constexpr ClassShape kClassShapes[kNumClasses] = {
+    {1, 0, 0, 0},   // one-centre LJ
+    {2, 0, 0, 1},   // two-centre LJ + linear quadrupole
+    {1, 3, 0, 0},   // LJ + up to three charges (water-like, ions)
+    {1, 0, 1, 0},   // Stockmayer
+    {2, 2, 1, 1},   // small mixed
+    {4, 4, 2, 2},   // general
+};
+__host__ __device__ constexpr int class_reals(int c) {
+  return 3 * (kClassShapes[c].lj + kClassShapes[c].ch) + 6 * (kClassShapes[c].dp + kClassShapes[c].qd);
+}
+
+// Species table, grouped by site type (order within a type kept).
+struct SpeciesDev {
+  int nlj, nch, ndp, nqd;
+  int rot_dof;      // number of non-zero principal moments
+  int lj_type0;     // first RDF LJ-site type index of this species
+  double mass;
+  double inertia[3];
+  double net_charge;
+  double lj_pos[kMaxS][3];
+  double ch_pos[kMaxS][3];
+  double dp_pos[kMaxS][3], dp_axis[kMaxS][3];
+  double qd_pos[kMaxS][3], qd_axis[kMaxS][3];
+  double ch_q[kMaxS], dp_mu[kMaxS], qd_Q[kMaxS];
+  double lj_sigma[kMaxS], lj_eps[kMaxS];
+};
+
+struct SpeciesTable {
+  int nsp;
+  int n_lj_types;
+  int nsite_pair[kMaxSp][kMaxSp];                  // interacting site pairs per molecule pair
+  SpeciesDev sp[kMaxSp];
+  // 4 eps sigma^6 and 4 eps sigma^12 for LJ site a of A and b of B
+  double c6[kMaxSp][kMaxS][kMaxSp][kMaxS];
+  double c12[kMaxSp][kMaxS][kMaxSp][kMaxS];
+};
+
+// Per-system constants derived on the host from ms2_params.
+struct SysParams {
+  double L, invL, rc, rc2, V;
+  double ke, krf, crf;
+  double alpha, alpha2, gpref;                     // gpref = 2 alpha / sqrt(pi)
+  int elec, kmax2, nk, lrc;
+  int precision, cls, nsp, pad;
+  // LJ tail per species pair: multiply by N_A N_B (already includes 2 pi / V)
+  double lrc_u[kMaxSp][kMaxSp], lrc_us[kMaxSp][kMaxSp], lrc_uss[kMaxSp][kMaxSp];
+  double ew_const[kMaxSp];                         // self + intramolecular per molecule
+};
+
+// Per-slot buffers (device pointers) and bookkeeping.
+struct SlotDev {
+  int n, npad;
+  int jsplits, item0, nitems;
+  int active;                 // 0: skipped by every kernel
+  int kchunks, mchunks;       // Ewald force / structure-factor partial counts
+  int com_ld;                 // row length of com/quat/force/torque arrays
+  int pad0;
+  const int* species;
+  const double* com;          // [3][com_ld]
+  const double* quat;         // [4][com_ld]
+  void* sites;                // [class_reals][npad] Real
+  double* pf;                 // [jsplits][6][npad] pair partial F, tau
+  double* bsum;               // [nitems][kNumBlockSums]
+  double* force;              // [3][com_ld]
+  double* torque;             // [3][com_ld]
+  double* sums;               // [MS2_NSUM]
+  double* sk_part;            // [mchunks][nk][2] structure-factor partials
+  double* sk;                 // [nk][2]
+  double* fk;                 // [kchunks][6][npad] reciprocal partial F, tau
+  double* kred;               // [kchunks][kblocks_m] sum_a d_a . F_a partials + [2] U, W_atomic
+  double* ksum;               // [4]: U_recip, W_atomic, sum d.F, spare
+  const struct KVec* kvec;    // [nk] half-space integer vectors
+  int nk, mtiles;             // k vectors; 64-molecule tiles of the force kernel
+};
+
+// Species indices come from caller memory: clamp them into the table so a
+// bad index can never address outside it.
+__host__ __device__ inline int clamp_species(int s, int nsp) {
+  return s < 0 ? 0 : (s >= nsp ? nsp - 1 : s);
+}
+
+struct WorkItem {
+  int slot, i0, j0, j1, part, pad0, pad1, pad2;
+};
+
+
+}  // namespace ms2

@@ -1,0 +1,255 @@
+// Ewald reciprocal space on gfx950 (the paper's Sec. 4: the long-range part
+// of the Coulomb sum is done in Fourier space).  Everything here is FP64:
+// charge positions are rebuilt from the centre and the quaternion in FP64,
+// phases are reduced to [-pi, pi] exactly via the integer period of the k
+// lattice, and S(k) is accumulated in FP64.
+//
+//   sk_kernel          (k block of 64) x (64-molecule tile): partial S(k)
+//   sk_reduce_kernel   per system: S(k) over tiles in fixed order, energy and
+//                      atomic virial of the reciprocal sum
+//   kforce_kernel      (64-molecule tile) x (128-k chunk): per-molecule force,
+//                      torque and sum d.F partials
+//   reduce_kspace_kernel per system: adds the partials (fixed order) into the
+//                      caller's force/torque and the sums
+// The k set is a half space (k and -k give equal contributions), so every
+// reciprocal term is doubled.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ms2 {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.14159265358979323846264338328;
+
+__device__ __forceinline__ void quat_rot(const double* q, int ld, int i, double A[3][3]) {
+  const double w = q[i], x = q[ld + i], y = q[2 * ld + i], z = q[3 * ld + i];
+  A[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  A[0][1] = 2.0 * (x * y - w * z);
+  A[0][2] = 2.0 * (x * z + w * y);
+  A[1][0] = 2.0 * (x * y + w * z);
+  A[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  A[1][2] = 2.0 * (y * z - w * x);
+  A[2][0] = 2.0 * (x * z - w * y);
+  A[2][1] = 2.0 * (y * z + w * x);
+  A[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// exp(i 2 pi t) with t reduced by its nearest integer first
+__device__ __forceinline__ void phase(double t, double& c, double& s) {
+  t -= rint(t);
+  sincospi(2.0 * t, &s, &c);
+}
+
+__global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slots,
+                                                const SysParams* __restrict__ prm,
+                                                const SpeciesTable* __restrict__ tab) {
+  __shared__ double s_x[kMolTile * kMaxS], s_y[kMolTile * kMaxS], s_z[kMolTile * kMaxS],
+      s_q[kMolTile * kMaxS];
+  const SlotDev& sd = slots[blockIdx.z];
+  const SysParams& P = prm[blockIdx.z];
+  if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
+  const int mc = blockIdx.y;
+  if (mc >= sd.mchunks || (int)blockIdx.x * 64 >= sd.nk) return;
+  const int tid = threadIdx.x, ld = sd.com_ld;
+  const int m0 = mc * kMolTile, m1 = min(sd.n, m0 + kMolTile);
+  int maxq = 0;
+  for (int s = 0; s < P.nsp; ++s) maxq = max(maxq, tab->sp[s].nch);
+  {
+    const int i = m0 + tid;
+    for (int a = 0; a < maxq; ++a) s_q[tid * kMaxS + a] = 0.0;
+    if (i < m1) {
+      const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], P.nsp)];
+      double A[3][3];
+      quat_rot(sd.quat, ld, i, A);
+      const double cx = sd.com[i], cy = sd.com[ld + i], cz = sd.com[2 * ld + i];
+      for (int a = 0; a < D.nch; ++a) {
+        const double* b = D.ch_pos[a];
+        s_x[tid * kMaxS + a] = cx + A[0][0] * b[0] + A[0][1] * b[1] + A[0][2] * b[2];
+        s_y[tid * kMaxS + a] = cy + A[1][0] * b[0] + A[1][1] * b[1] + A[1][2] * b[2];
+        s_z[tid * kMaxS + a] = cz + A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2];
+        s_q[tid * kMaxS + a] = D.ch_q[a];
+      }
+    }
+  }
+  __syncthreads();
+  const int k = blockIdx.x * 64 + tid;
+  if (k >= sd.nk) return;
+  const KVec kv = sd.kvec[k];
+  const double invL = P.invL;
+  double re = 0.0, im = 0.0;
+  for (int m = 0; m < m1 - m0; ++m)
+    for (int a = 0; a < maxq; ++a) {
+      const int e = m * kMaxS + a;
+      const double q = s_q[e];
+      if (q == 0.0) continue;
+      double c, s;
+      phase((kv.nx * s_x[e] + kv.ny * s_y[e] + kv.nz * s_z[e]) * invL, c, s);
+      re += q * c;
+      im += q * s;
+    }
+  double* out = sd.sk_part + ((size_t)mc * sd.nk + k) * 2;
+  out[0] = re;
+  out[1] = im;
+}
+
+__global__ __launch_bounds__(256) void sk_reduce_kernel(const SlotDev* __restrict__ slots,
+                                                        const SysParams* __restrict__ prm) {
+  __shared__ double s_u[256], s_w[256];
+  const SlotDev& sd = slots[blockIdx.x];
+  const SysParams& P = prm[blockIdx.x];
+  if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
+  const int tid = threadIdx.x;
+  const double k2s = (kTwoPi * P.invL) * (kTwoPi * P.invL);
+  double u = 0.0, w = 0.0;
+  for (int k = tid; k < sd.nk; k += 256) {
+    double re = 0.0, im = 0.0;
+    for (int mc = 0; mc < sd.mchunks; ++mc) {
+      re += sd.sk_part[((size_t)mc * sd.nk + k) * 2];
+      im += sd.sk_part[((size_t)mc * sd.nk + k) * 2 + 1];
+    }
+    sd.sk[2 * k] = re;
+    sd.sk[2 * k + 1] = im;
+    const double k2 = k2s * sd.kvec[k].n2;
+    const double g = exp(-k2 / (4.0 * P.alpha2)) / k2;
+    const double s2 = re * re + im * im;
+    u += g * s2;
+    w += g * s2 * (1.0 - k2 / (2.0 * P.alpha2));
+  }
+  s_u[tid] = u;
+  s_w[tid] = w;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      s_u[tid] += s_u[tid + h];
+      s_w[tid] += s_w[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double pre = 2.0 * P.ke * kTwoPi / P.V;  // 2 pi k_e / V, doubled for the half space
+    sd.ksum[0] = pre * s_u[0];
+    sd.ksum[1] = pre * s_w[0];
+  }
+}
+
+__global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ slots,
+                                                    const SysParams* __restrict__ prm,
+                                                    const SpeciesTable* __restrict__ tab) {
+  __shared__ double s_re[kKChunk], s_im[kKChunk], s_g[kKChunk];
+  __shared__ int s_n[kKChunk][3];
+  __shared__ double s_red[64];
+  const SlotDev& sd = slots[blockIdx.z];
+  const SysParams& P = prm[blockIdx.z];
+  if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
+  const int kc = blockIdx.y;
+  if (kc >= sd.kchunks || (int)blockIdx.x >= sd.mtiles) return;
+  const int tid = threadIdx.x, ld = sd.com_ld, np = sd.npad;
+  const int k0 = kc * kKChunk, nkc = min(kKChunk, sd.nk - k0);
+  const double k2s = (kTwoPi * P.invL) * (kTwoPi * P.invL);
+  for (int e = tid; e < nkc; e += 64) {
+    const KVec kv = sd.kvec[k0 + e];
+    s_re[e] = sd.sk[2 * (k0 + e)];
+    s_im[e] = sd.sk[2 * (k0 + e) + 1];
+    const double k2 = k2s * kv.n2;
+    s_g[e] = exp(-k2 / (4.0 * P.alpha2)) / k2;
+    s_n[e][0] = kv.nx;
+    s_n[e][1] = kv.ny;
+    s_n[e][2] = kv.nz;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 64 + tid;
+  double dF = 0.0;
+  if (i < sd.n) {
+    const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], P.nsp)];
+    double A[3][3];
+    quat_rot(sd.quat, ld, i, A);
+    const double cx = sd.com[i], cy = sd.com[ld + i], cz = sd.com[2 * ld + i];
+    double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+    // F_a = (4 pi k_e q_a / V) sum_k g(k) k Im(e^{i k.r_a} S(k)^*), doubled
+    const double pre = 2.0 * P.ke * 4.0 * kPi / P.V;
+    for (int a = 0; a < D.nch; ++a) {
+      const double* b = D.ch_pos[a];
+      const double d[3] = {A[0][0] * b[0] + A[0][1] * b[1] + A[0][2] * b[2],
+                           A[1][0] * b[0] + A[1][1] * b[1] + A[1][2] * b[2],
+                           A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2]};
+      const double x = cx + d[0], y = cy + d[1], z = cz + d[2];
+      double sx = 0.0, sy = 0.0, sz = 0.0;
+      for (int e = 0; e < nkc; ++e) {
+        double c, s;
+        phase((s_n[e][0] * x + s_n[e][1] * y + s_n[e][2] * z) * P.invL, c, s);
+        const double t = s_g[e] * (s * s_re[e] - c * s_im[e]);
+        sx += t * s_n[e][0];
+        sy += t * s_n[e][1];
+        sz += t * s_n[e][2];
+      }
+      const double f = pre * D.ch_q[a] * kTwoPi * P.invL;
+      const double fa[3] = {f * sx, f * sy, f * sz};
+      F[0] += fa[0]; F[1] += fa[1]; F[2] += fa[2];
+      T[0] += d[1] * fa[2] - d[2] * fa[1];
+      T[1] += d[2] * fa[0] - d[0] * fa[2];
+      T[2] += d[0] * fa[1] - d[1] * fa[0];
+      dF += d[0] * fa[0] + d[1] * fa[1] + d[2] * fa[2];
+    }
+    double* out = sd.fk + (size_t)kc * 6 * np;
+    for (int c = 0; c < 3; ++c) {
+      out[c * np + i] = F[c];
+      out[(3 + c) * np + i] = T[c];
+    }
+  }
+  s_red[tid] = dF;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (tid < h) s_red[tid] += s_red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) sd.kred[(size_t)kc * sd.mtiles + blockIdx.x] = s_red[0];
+}
+
+__global__ __launch_bounds__(256) void reduce_kspace_kernel(const SlotDev* __restrict__ slots,
+                                                            const SysParams* __restrict__ prm) {
+  __shared__ double s_d[256];
+  const SlotDev& sd = slots[blockIdx.x];
+  const SysParams& P = prm[blockIdx.x];
+  if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
+  const int tid = threadIdx.x, np = sd.npad, ld = sd.com_ld;
+  for (int i = tid; i < sd.n; i += 256) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int kc = 0; kc < sd.kchunks; ++kc)
+      for (int c = 0; c < 6; ++c) v[c] += sd.fk[((size_t)kc * 6 + c) * np + i];
+    for (int c = 0; c < 3; ++c) {
+      sd.force[c * ld + i] += v[c];
+      sd.torque[c * ld + i] += v[3 + c];
+    }
+  }
+  const int nr = sd.kchunks * sd.mtiles;
+  const int per = (nr + 255) / 256;
+  double d = 0.0;
+  for (int t = tid * per; t < min(nr, (tid + 1) * per); ++t) d += sd.kred[t];
+  s_d[tid] = d;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) s_d[tid] += s_d[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double w_mol = sd.ksum[1] - s_d[0];  // molecular virial: W_atomic - sum d.F
+    sd.sums[MS2_SUM_U_RECIP] += sd.ksum[0];
+    sd.sums[MS2_SUM_VIRIAL] += w_mol;
+    sd.sums[MS2_SUM_US] -= w_mol;
+  }
+}
+
+hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
+                         int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
+                         int max_kchunks, hipStream_t st) {
+  hipLaunchKernelGGL(sk_kernel, dim3(max_kblocks, max_mchunks, nslots), dim3(64), 0, st, slots,
+                     prm, tab);
+  hipLaunchKernelGGL(sk_reduce_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
+  hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
+                     prm, tab);
+  hipLaunchKernelGGL(reduce_kspace_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
+  return hipGetLastError();
+}
+
+}  // namespace ms2

@@ -315,6 +315,15 @@ def batched_state_point(s: int, master_seed: int = 4, n_lo: int = 500, n_hi: int
     return sysm
 
 
+def jittered(system: System, amplitude: float, seed: int) -> System:
+    """Same system with every centre displaced by a uniform random vector of
+    at most `amplitude` per component (wrapped into the box)."""
+    rng = np.random.default_rng(seed)
+    out = system.copy()
+    out.com = (system.com + rng.uniform(-amplitude, amplitude, system.com.shape)) % system.params.box
+    return out
+
+
 def with_random_positions(system: System, seed: int) -> System:
     """Same model, uniformly random centres and orientations (for parity tests
     that need unstructured geometry)."""

@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libms2.so (include/ms2.h).
+
+Argument marshalling only: every step of the force/energy path runs in the
+HIP kernels of the library.  Torch is used for device memory and streams.
+The binding raises if the compiled library is missing or no HIP device is
+present; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libms2.so")
+
+MAX_SITES = 8
+MAX_SPECIES = 8
+NSUM = 12
+SUM_NAMES = ["u_lj", "u_elec", "u_recip", "u_const", "u_lrc", "virial", "us", "uss",
+             "us_lrc", "uss_lrc", "npair", "nsite"]
+FP64, FP32 = 0, 1
+STEP_GRAPH = 1
+STATUS = {0: "MS2_OK", 1: "MS2_EINVAL", 2: "MS2_ENOMEM", 3: "MS2_EDEVICE", 4: "MS2_ENONFINITE",
+          5: "MS2_EFULL"}
+
+c_double, c_int32, c_int64, c_size_t, c_void_p = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
+                                                  ctypes.c_size_t, ctypes.c_void_p)
+P = ctypes.POINTER
+
+
+class Species(ctypes.Structure):
+    _fields_ = [("n_sites", c_int32), ("type", c_int32 * MAX_SITES),
+                ("pos", (c_double * 3) * MAX_SITES), ("axis", (c_double * 3) * MAX_SITES),
+                ("sigma", c_double * MAX_SITES), ("eps", c_double * MAX_SITES),
+                ("mag", c_double * MAX_SITES), ("mass", c_double), ("inertia", c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("box", c_double), ("rc", c_double), ("eps_rf", c_double), ("alpha", c_double),
+                ("coulomb_k", c_double), ("elec", c_int32), ("kmax2", c_int32), ("lj_lrc", c_int32),
+                ("precision", c_int32)]
+
+
+class System(ctypes.Structure):
+    _fields_ = [("params", Params), ("n_mol", c_int32), ("integrator", c_int32), ("n_steps", c_int64),
+                ("dt", c_double), ("temperature", c_double), ("sample_every", c_int32),
+                ("rdf_every", c_int32), ("rdf_bins", c_int32), ("acf_every", c_int32),
+                ("acf_origin_every", c_int32), ("acf_nlag", c_int32), ("rdf_rmax", c_double),
+                ("u0", c_double), ("h_species", P(c_int32)), ("h_com", P(c_double)),
+                ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double))]
+
+
+class Samples(ctypes.Structure):
+    _fields_ = [("steps_done", c_int64), ("status", c_int32), ("rdf_ntypes", c_int32),
+                ("sums", c_double * NSUM), ("ekin_trans", c_double), ("ekin_rot", c_double),
+                ("moments", c_double * 11), ("h_rdf", P(c_double)), ("h_acf_v", P(c_double)),
+                ("h_acf_j", P(c_double)), ("h_acf_cnt", P(c_double)), ("h_com", P(c_double)),
+                ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double)),
+                ("h_force", P(c_double)), ("h_torque", P(c_double))]
+
+
+class MS2Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTED = ["ms2_create", "ms2_destroy", "ms2_forces", "ms2_ewald_kspace", "ms2_batch_create",
+            "ms2_batch_destroy", "ms2_slot_footprint", "ms2_slot_admit", "ms2_slot_retire",
+            "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_last_error"]
+
+
+def lib():
+    """Load libms2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1507_07548_amd.build.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = c_void_p, P(c_double), P(c_int32)
+        L.ms2_create.argtypes = [P(vp), P(Species), c_int32, c_int32]
+        L.ms2_destroy.argtypes = [vp]
+        L.ms2_destroy.restype = None
+        for fn in (L.ms2_forces, L.ms2_ewald_kspace):
+            fn.argtypes = [vp, P(Params), c_int32, vp, vp, vp, vp, vp, vp, vp]
+        L.ms2_batch_create.argtypes = [vp, c_int32, c_size_t, P(vp)]
+        L.ms2_batch_destroy.argtypes = [vp]
+        L.ms2_batch_destroy.restype = None
+        L.ms2_slot_footprint.argtypes = [vp, P(System), P(c_size_t)]
+        L.ms2_slot_admit.argtypes = [vp, P(System), P(c_int32), vp]
+        L.ms2_slot_retire.argtypes = [vp, c_int32]
+        L.ms2_step.argtypes = [vp, c_int32, c_int32, vp]
+        L.ms2_sample.argtypes = [vp, c_int32, P(Samples), vp]
+        L.ms2_slot_status.argtypes = [vp, c_int32, P(c_int64), P(c_int32), vp]
+        L.ms2_tile_config.argtypes = [vp, c_int32, c_int32, P(c_int32), P(c_int32)]
+        L.ms2_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("ms2_destroy", "ms2_batch_destroy", "ms2_last_error"):
+                getattr(L, name).restype = c_int32
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        raise MS2Error(status, lib().ms2_last_error().decode())
+
+
+def species_array(species) -> ctypes.Array:
+    """Marshal a list of inputs.Species into ms2_species[]."""
+    arr = (Species * len(species))()
+    for k, s in enumerate(species):
+        o = arr[k]
+        o.n_sites = len(s.sites)
+        for a, site in enumerate(s.sites):
+            o.type[a] = int(site.kind)
+            for c in range(3):
+                o.pos[a][c] = float(site.pos[c])
+                o.axis[a][c] = float(site.axis[c])
+            o.sigma[a], o.eps[a], o.mag[a] = float(site.sigma), float(site.eps), float(site.mag)
+        o.mass = float(s.mass)
+        for c in range(3):
+            o.inertia[c] = float(s.inertia[c])
+    return arr
+
+
+def params_struct(p, precision: int) -> Params:
+    return Params(box=p.box, rc=p.rc, eps_rf=p.eps_rf, alpha=p.alpha, coulomb_k=p.coulomb_k,
+                  elec=p.elec, kmax2=p.kmax2, lj_lrc=p.lj_lrc, precision=precision)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """ms2_ctx: a species table on one HIP device."""
+
+    def __init__(self, species: Sequence, device: int = 0):
+        self.species = list(species)
+        self._arr = species_array(self.species)
+        h = c_void_p()
+        check(lib().ms2_create(ctypes.byref(h), self._arr, len(self.species), device))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().ms2_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forces(self, params: Params, n: int, species, com, quat, force, torque, sums, stream=None):
+        """ms2_forces on torch device tensors (SoA layouts of include/ms2.h)."""
+        check(lib().ms2_forces(self.handle, ctypes.byref(params), n, species.data_ptr(), com.data_ptr(),
+                               quat.data_ptr(), force.data_ptr(), torque.data_ptr(), sums.data_ptr(),
+                               _stream_ptr(stream)))
+
+    def ewald_kspace(self, params: Params, n: int, species, com, quat, force, torque, sums, stream=None):
+        check(lib().ms2_ewald_kspace(self.handle, ctypes.byref(params), n, species.data_ptr(),
+                                     com.data_ptr(), quat.data_ptr(), force.data_ptr(), torque.data_ptr(),
+                                     sums.data_ptr(), _stream_ptr(stream)))
+
+    def tile_config(self, n: int, precision: int):
+        w, j = c_int32(), c_int32()
+        check(lib().ms2_tile_config(self.handle, n, precision, ctypes.byref(w), ctypes.byref(j)))
+        return w.value, j.value
+
+
+class DeviceSystem:
+    """Device-resident SoA copies of one system's inputs and outputs."""
+
+    def __init__(self, system, device: str = "cuda:0"):
+        import torch
+        self.n = system.n
+        self.species = torch.tensor(np.ascontiguousarray(system.species_idx, dtype=np.int32), device=device)
+        self.com = torch.tensor(np.ascontiguousarray(system.com.T), dtype=torch.float64, device=device)
+        self.quat = torch.tensor(np.ascontiguousarray(system.quat.T), dtype=torch.float64, device=device)
+        self.force = torch.zeros((3, self.n), dtype=torch.float64, device=device)
+        self.torque = torch.zeros((3, self.n), dtype=torch.float64, device=device)
+        self.sums = torch.zeros(NSUM, dtype=torch.float64, device=device)
+
+
+def evaluate(ctx: Context, system, precision: int = FP64, dev: Optional[DeviceSystem] = None,
+             stream=None):
+    """One full force/energy evaluation of `system` on the GPU (ms2_forces,
+    plus ms2_ewald_kspace with Ewald).  Returns numpy (force[n,3],
+    torque[n,3], sums[NSUM])."""
+    import torch
+    d = dev or DeviceSystem(system)
+    p = params_struct(system.params, precision)
+    ctx.forces(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums, stream)
+    if system.params.elec == 2:
+        ctx.ewald_kspace(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums, stream)
+    torch.cuda.synchronize()
+    return d.force.cpu().numpy().T.copy(), d.torque.cpu().numpy().T.copy(), d.sums.cpu().numpy().copy()

@@ -1,0 +1,216 @@
+"""GPU parity of the force/energy/virial path (ms2_forces, ms2_ewald_kspace)
+against the FP64 CPU oracle, element by element on the same seeded inputs.
+
+Tolerances (derived from the arithmetic):
+  FP64 pairs:  max_i |dF_i| <= 1e-11 rms|F| (same for torques); every sum
+               within 1e-11 relative (+1e-12 of the summed magnitudes) --
+               differences come only from summation order and 1-ulp
+               differences of rsqrt/erfc.
+  FP32 pairs:  max_i |dF_i| <= 1e-5 rms|F|; total energy relative to the
+               summed magnitudes of its terms: each FP32 pair energy carries
+               ~2e-7 relative rounding (the rounding of r^2 is tripled by
+               r^-6), so the sum over ~1e6 pairs lands at 1e-9..1e-8 for
+               disordered LJ fluids (<= 1e-8 asserted at N = 4000, 8192),
+               <= 5e-8 for the dense 2CLJQ fluid near its lattice start,
+               <= 2e-7 for water + ions (site-site Coulomb terms cancel to
+               ~1 % of their magnitudes), <= 1e-6 on perfect lattices (every
+               pair of a shell rounds the same way, so errors add coherently);
+               virial, U_s, U_ss 1e-6 relative.  Site arithmetic in FP32,
+               accumulation in FP64 per molecule pair.
+  Counters (accepted pairs, site pairs): exact -- the cut-off decision is
+  taken in FP64 with the same rounding on both sides.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from models import ionic_pair_species, offset_multipoles, small_system
+from paper_1507_07548_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1507_07548_amd import ms2  # noqa: E402
+
+NPAIR, NSITE = 10, 11
+U_SLOTS = [0, 1, 2, 3, 4]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare(system, precision, ctx=None, label=""):
+    say(f"[gpu] {label} n={system.n} precision={'fp32' if precision else 'fp64'}")
+    ctx = ctx or ms2.Context(system.species)
+    f, t, s = ms2.evaluate(ctx, system, precision)
+    fo, to, so = oracle.evaluate(system)
+    rms_f = np.sqrt((fo ** 2).sum(1).mean())
+    rms_t = np.sqrt((to ** 2).sum(1).mean())
+    rms_f = rms_f if rms_f > 0 else 1.0     # no pair inside the cut-off: absolute error
+    rms_t = rms_t if rms_t > 0 else 1.0
+    err_f = np.abs(f - fo).max() / rms_f
+    err_t = np.abs(t - to).max() / rms_t
+    assert s[NPAIR] == so[NPAIR] and s[NSITE] == so[NSITE], (s[NPAIR], so[NPAIR], s[NSITE], so[NSITE])
+    return f, t, s, fo, to, so, err_f, err_t
+
+
+def energy_error(s, so):
+    """|U - U_oracle| over the summed magnitudes of the energy terms."""
+    du = abs(s[U_SLOTS].sum() - so[U_SLOTS].sum())
+    scale = np.abs(so[U_SLOTS]).sum()
+    say(f"  energy rel err {du / scale:.3e}; per term " +
+        " ".join(f"{abs(s[k] - so[k]) / max(abs(so[k]), 1e-300):.1e}" for k in U_SLOTS))
+    return du / scale
+
+
+def check_sums(s, so, rtol, atol_frac, slots=range(10)):
+    scale = np.abs(so[:10]).sum()
+    for k in slots:
+        assert abs(s[k] - so[k]) <= rtol * abs(so[k]) + atol_frac * scale, (k, s[k], so[k])
+
+
+# --------------------------------------------------------------------------
+# the three single-system workloads
+# --------------------------------------------------------------------------
+def test_lj_fluid_fp64_parity():
+    # the perfect FCC start has zero net force on every molecule; displace it
+    s = I.jittered(I.lj_fluid(), 0.05, seed=11)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="lj_fluid")
+    assert ef < 1e-11
+    check_sums(su, so, 1e-11, 1e-12)
+
+
+def test_lj_fluid_lattice_start():
+    s = I.lj_fluid()
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="lj_fluid lattice")
+    assert np.abs(f).max() < 1e-11 and np.abs(fo).max() < 1e-11
+    check_sums(su, so, 1e-11, 1e-12)
+    f32, _, s32 = ms2.evaluate(ms2.Context(s.species), s, ms2.FP32)
+    assert np.abs(f32).max() < 1e-4
+    assert energy_error(s32, so) < 1e-6      # coherent rounding on a lattice
+
+
+def test_quadrupolar_fluid_fp64_parity():
+    s = I.quadrupolar_fluid()
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="quadrupolar_fluid")
+    assert ef < 1e-11 and et < 1e-11, (ef, et)
+    check_sums(su, so, 1e-11, 1e-12)
+
+
+def test_quadrupolar_fluid_fp32_parity():
+    s = I.quadrupolar_fluid()
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="quadrupolar_fluid")
+    say(f"  fp32 max|dF|/rms {ef:.3e} max|dT|/rms {et:.3e}")
+    assert ef < 1e-5 and et < 1e-5
+    assert energy_error(su, so) < 1e-6           # FCC start
+    check_sums(su, so, 1e-6, 1e-8, slots=[5, 6, 7, 8, 9])
+    sj = I.jittered(s, 0.1, seed=5)               # disordered
+    f, t, su, fo, to, so, ef, et = compare(sj, ms2.FP32, label="quadrupolar_fluid jittered")
+    assert ef < 1e-5 and et < 1e-5
+    assert energy_error(su, so) < 5e-8
+    check_sums(su, so, 1e-6, 1e-8, slots=[5, 6, 7, 8, 9])
+
+
+def test_ionic_solution_fp64_parity():
+    s = I.ionic_solution()
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="ionic_solution")
+    say(f"  fp64 max|dF|/rms {ef:.3e} max|dT|/rms {et:.3e}")
+    assert ef < 1e-11 and et < 1e-11
+    check_sums(su, so, 1e-11, 1e-12)
+
+
+def test_ionic_solution_fp32_parity():
+    s = I.ionic_solution()
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="ionic_solution")
+    say(f"  fp32 max|dF|/rms {ef:.3e} max|dT|/rms {et:.3e}")
+    assert ef < 1e-5 and et < 1e-5
+    assert energy_error(su, so) < 1e-6
+    # reciprocal part is FP64 in both precision forms
+    assert abs(su[2] - so[2]) <= 1e-10 * abs(so[2])
+    sj = I.jittered(s, 0.3, seed=6)
+    f, t, su, fo, to, so, ef, et = compare(sj, ms2.FP32, label="ionic_solution jittered")
+    assert ef < 1e-5 and et < 1e-5
+    assert energy_error(su, so) < 2e-7
+
+
+# --------------------------------------------------------------------------
+# every site type, ragged sizes, reaction field on charges and dipoles
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3, 63, 65, 130, 257])
+@pytest.mark.parametrize("elec", [I.ELEC_NONE, I.ELEC_RF])
+def test_offset_multipoles_ragged(n, elec):
+    box = 1.4 * n ** (1 / 3) + 2.5
+    s = small_system([offset_multipoles(), I.stockmayer()], n, box, 0.45 * box, seed=n + 7 * elec,
+                     elec=elec, eps_rf=25.0)
+    for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
+        f, t, su, fo, to, so, ef, et = compare(s, prec, label=f"offset elec={elec}")
+        assert ef < tol and et < tol, (ef, et)
+
+
+@pytest.mark.parametrize("n", [2, 37, 200])
+def test_ewald_mixture_ragged(n):
+    box = 1.3 * n ** (1 / 3) + 3.0
+    s = small_system(ionic_pair_species(), n, box, 0.45 * box, seed=n, elec=I.ELEC_EWALD,
+                     alpha=6.0 / box, kmax2=30)
+    for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
+        f, t, su, fo, to, so, ef, et = compare(s, prec, label="ewald mixture")
+        assert ef < tol and et < tol, (ef, et)
+        assert abs(su[2] - so[2]) <= 1e-10 * abs(so[2])
+
+
+def test_no_pair_inside_cutoff():
+    s = small_system([I.two_center_lj_quadrupole()], 8, 40.0, 3.0, seed=1, elec=I.ELEC_RF, jitter=0.0)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="dilute")
+    assert su[NPAIR] == 0 and np.abs(f).max() == 0.0 and su[0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# full sizes: N = 4000 and 8192 (largest state point and serving size)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [4000, 8192])
+def test_large_quadrupolar_fluid_fp32(n):
+    s = I.jittered(I.quadrupolar_fluid(n=n, density=0.45), 0.1, seed=n)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="large")
+    say(f"  fp32 n={n} max|dF|/rms {ef:.3e}")
+    assert ef < 1e-5 and et < 1e-5
+    assert energy_error(su, so) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# determinism and argument errors
+# --------------------------------------------------------------------------
+def test_repeat_is_bitwise_identical():
+    s = I.quadrupolar_fluid()
+    ctx = ms2.Context(s.species)
+    a = ms2.evaluate(ctx, s, ms2.FP32)
+    b = ms2.evaluate(ctx, s, ms2.FP32)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_argument_errors_are_reported_before_launch():
+    s = I.quadrupolar_fluid(n=64)
+    ctx = ms2.Context(s.species)
+    d = ms2.DeviceSystem(s)
+    bad = ms2.params_struct(s.params, ms2.FP32)
+    bad.rc = 0.6 * bad.box
+    with pytest.raises(ms2.MS2Error) as e:
+        ctx.forces(bad, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    assert e.value.status == 1
+    good = ms2.params_struct(s.params, ms2.FP32)
+    with pytest.raises(ms2.MS2Error):
+        ctx.ewald_kspace(good, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    with pytest.raises(ms2.MS2Error):
+        ctx.forces(good, 1, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    ew = ms2.params_struct(s.params, ms2.FP32)
+    ew.elec, ew.alpha, ew.kmax2 = 2, 1.0, 10
+    with pytest.raises(ms2.MS2Error):   # quadrupoles with Ewald
+        ctx.forces(ew, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
