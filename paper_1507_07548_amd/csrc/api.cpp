@@ -18,12 +18,12 @@
 #include "internal.h"
 
 namespace ms2 {
-hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SpeciesTable* tab,
-                             int nslots, int max_n, hipStream_t st);
+hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
+                             const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
 hipError_t launch_pair(int cls, int precision, int waves, const WorkItem* items, int base,
                        int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
-hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots,
+hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st);
 hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
                          int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
@@ -292,10 +292,10 @@ TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
   return c;
 }
 
-void build_items(int n, const TileCfg& c, int slot, int item0, std::vector<WorkItem>& out,
-                 int* jsplits) {
+int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits) {
   const int it = 64 * c.waves;
   const int js = (n + c.jchunk - 1) / c.jchunk;
+  int local = 0;
   for (int i0 = 0; i0 < n; i0 += it)
     for (int p = 0; p < js; ++p) {
       WorkItem w{};
@@ -304,10 +304,11 @@ void build_items(int n, const TileCfg& c, int slot, int item0, std::vector<WorkI
       w.j0 = p * c.jchunk;
       w.j1 = std::min(n, (p + 1) * c.jchunk);
       w.part = p;
+      w.local = local++;
       out.push_back(w);
     }
-  (void)item0;
   *jsplits = js;
+  return local;
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +346,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   if (ic == ctx->item_cache.end()) {
     std::vector<WorkItem> items;
     int js = 0;
-    build_items(n, cfg, 0, 0, items, &js);
+    build_items(n, cfg, 0, items, &js);
     DevBuf b;
     MS2_HIP(b.ensure(items.size() * sizeof(WorkItem)));
     MS2_HIP(hipMemcpy(b.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
@@ -382,7 +383,6 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   d.n = n;
   d.npad = npad;
   d.jsplits = js;
-  d.item0 = 0;
   d.nitems = nitems;
   d.active = 1;
   d.kchunks = kchunks;
@@ -498,10 +498,10 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
                               d_sums, false, st, &r, &cfg, &nitems);
   if (s != MS2_OK) return s;
   const ms2::CachedItems& ci = ctx->item_cache[std::make_tuple(n_mol, cfg.waves, cfg.jchunk)];
-  MS2_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, ctx->d_tab, 1, n_mol, st));
+  MS2_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n_mol, st));
   MS2_HIP(launch_pair(ctx->cls, h_params->precision, cfg.waves, (const WorkItem*)ci.buf.p, 0, nitems,
                       r->d_slot, r->d_prm, ctx->d_tab, st));
-  MS2_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, st));
+  MS2_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, n_mol, st));
   MS2_HIP(hipEventRecord(r->ev, st));
   return MS2_OK;
 }

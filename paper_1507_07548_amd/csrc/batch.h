@@ -64,6 +64,5 @@ ms2_status check_params(const ms2_ctx* ctx, const ms2_params* p);
 void build_sys_params(const ms2_ctx* ctx, const ms2_params* p, int nk, SysParams& s);
 ms2_status kvec_table(ms2_ctx* ctx, int kmax2, const KVec** d_out, int* nk);
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n);
-void build_items(int n, const TileCfg& c, int slot, int item0, std::vector<WorkItem>& out,
-                 int* jsplits);
+int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits);
 }  // namespace ms2

@@ -84,10 +84,12 @@ __device__ __forceinline__ void rot_matrix(double w, double x, double y, double 
 
 template <typename Real, int C>
 __global__ __launch_bounds__(256) void site_frame_kernel(const SlotDev* __restrict__ slots,
+                                                         const SysParams* __restrict__ prm,
                                                          const SpeciesTable* __restrict__ tab) {
   constexpr ClassShape S = kClassShapes[C];
   const SlotDev& sd = slots[blockIdx.y];
   if (!sd.active) return;
+  if (prm[blockIdx.y].precision != (sizeof(Real) == 4 ? MS2_FP32 : MS2_FP64)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= sd.n) return;
   const int ld = sd.com_ld, np = sd.npad;
@@ -623,40 +625,50 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
       for (int k = 0; k < kNumBlockSums; ++k) s_red[k][tid] += s_red[k][tid + h];
     __syncthreads();
   }
-  if (tid < kNumBlockSums) sd.bsum[(size_t)(gitem - sd.item0) * kNumBlockSums + tid] = s_red[tid][0];
+  if (tid < kNumBlockSums) sd.bsum[(size_t)it.local * kNumBlockSums + tid] = s_red[tid][0];
 }
 
 // ---------------------------------------------------------------------------
-// Fixed-order reduction of the pair partials: forces/torques over j ranges,
-// block sums over items, constants (Ewald self/intramolecular, LJ tail) from
-// the species composition.  One block per slot.  OVERWRITES force, torque
-// and sums.
+// Fixed-order reductions of the pair partials.
+//  reduce_force_kernel: one thread per molecule sums its j-range partials in
+//    order; grid (molecule blocks, slots).  OVERWRITES force and torque.
+//  reduce_sums_kernel: one block per slot; item sums (each thread a
+//    contiguous run, then a tree), species counts, Ewald constants and the LJ
+//    tail.  OVERWRITES sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_pair_kernel(const SlotDev* __restrict__ slots,
+__global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __restrict__ slots) {
+  const SlotDev& sd = slots[blockIdx.y];
+  if (!sd.active) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= sd.n) return;
+  const int np = sd.npad, ld = sd.com_ld;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int p = 0; p < sd.jsplits; ++p)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] += sd.pf[((size_t)p * 6 + c) * np + i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    sd.force[c * ld + i] = v[c];
+    sd.torque[c * ld + i] = v[3 + c];
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restrict__ slots,
                                                           const SysParams* __restrict__ prm) {
   __shared__ double s_red[kNumBlockSums][256];
   __shared__ int s_cnt[kMaxSp][256];
   const SlotDev& sd = slots[blockIdx.x];
   if (!sd.active) return;
   const SysParams& P = prm[blockIdx.x];
-  const int tid = threadIdx.x, n = sd.n, np = sd.npad, ld = sd.com_ld;
+  const int tid = threadIdx.x, n = sd.n;
   int cnt[kMaxSp];
 #pragma unroll
   for (int s = 0; s < kMaxSp; ++s) cnt[s] = 0;
   for (int i = tid; i < n; i += 256) {
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int p = 0; p < sd.jsplits; ++p)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] += sd.pf[((size_t)p * 6 + c) * np + i];
-    for (int c = 0; c < 3; ++c) {
-      sd.force[c * ld + i] = v[c];
-      sd.torque[c * ld + i] = v[3 + c];
-    }
     const int s = clamp_species(sd.species[i], P.nsp);
 #pragma unroll
     for (int x = 0; x < kMaxSp; ++x) cnt[x] += (s == x);
   }
-  // items: each thread sums a contiguous run, then a tree over threads
   const int ni = sd.nitems;
   const int per = (ni + 255) / 256;
   double acc[kNumBlockSums] = {0, 0, 0, 0, 0, 0};
@@ -709,19 +721,19 @@ __global__ __launch_bounds__(256) void reduce_pair_kernel(const SlotDev* __restr
 // launchers
 // ---------------------------------------------------------------------------
 template <typename Real, int C>
-static hipError_t launch_frame_c(const SlotDev* slots, const SpeciesTable* tab, int nslots,
-                                 int max_n, hipStream_t st) {
+static hipError_t launch_frame_c(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
+                                 int nslots, int max_n, hipStream_t st) {
   dim3 grid((max_n + 255) / 256, nslots);
-  hipLaunchKernelGGL((site_frame_kernel<Real, C>), grid, dim3(256), 0, st, slots, tab);
+  hipLaunchKernelGGL((site_frame_kernel<Real, C>), grid, dim3(256), 0, st, slots, prm, tab);
   return hipGetLastError();
 }
 
-hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots,
+hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st) {
-#define MS2_FRAME_CASE(C)                                                                  \
-  case C:                                                                                  \
-    return precision == MS2_FP32 ? launch_frame_c<float, C>(slots, tab, nslots, max_n, st) \
-                                 : launch_frame_c<double, C>(slots, tab, nslots, max_n, st);
+#define MS2_FRAME_CASE(C)                                                                       \
+  case C:                                                                                       \
+    return precision == MS2_FP32 ? launch_frame_c<float, C>(slots, prm, tab, nslots, max_n, st) \
+                                 : launch_frame_c<double, C>(slots, prm, tab, nslots, max_n, st);
   switch (cls) {
     MS2_FRAME_CASE(0)
     MS2_FRAME_CASE(1)
@@ -773,9 +785,10 @@ hipError_t launch_pair(int cls, int precision, int waves, const WorkItem* items,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots,
+hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_pair_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
+  hipLaunchKernelGGL(reduce_force_kernel, dim3((max_n + 255) / 256, nslots), dim3(256), 0, st, slots);
+  hipLaunchKernelGGL(reduce_sums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();
 }
 

@@ -78,11 +78,11 @@ struct SysParams {
 // Per-slot buffers (device pointers) and bookkeeping.
 struct SlotDev {
   int n, npad;
-  int jsplits, item0, nitems;
+  int jsplits, nitems;
   int active;                 // 0: skipped by every kernel
   int kchunks, mchunks;       // Ewald force / structure-factor partial counts
-  int com_ld;                 // row length of com/quat/force/torque arrays
-  int pad0;
+  int com_ld;                 // row length of com/quat/force/torque (and slot state) arrays
+  int pad0, pad1;
   const int* species;
   const double* com;          // [3][com_ld]
   const double* quat;         // [4][com_ld]
@@ -107,8 +107,42 @@ __host__ __device__ inline int clamp_species(int s, int nsp) {
   return s < 0 ? 0 : (s >= nsp ? nsp - 1 : s);
 }
 
+// A pair-kernel work item: molecules [i0, i0 + 64 W) of a slot against
+// j in [j0, j1); `part` selects the per-molecule partial buffer, `local` the
+// item's block-sum row within its slot.
 struct WorkItem {
-  int slot, i0, j0, j1, part, pad0, pad1, pad2;
+  int slot, i0, j0, j1, part, local, pad1, pad2;
+};
+
+constexpr int kNumMoments = 11;   // N, X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ
+constexpr int kMdThreads = 1024;  // one block per slot for the O(N) step kernels
+
+// Per-slot integrator and sampler state (device memory).
+struct MDDev {
+  int active;            // 1 while steps_done < steps_target and status == OK
+  int integrator;        // MS2_VV or MS2_GEAR
+  int rotating;          // any species with a non-zero moment of inertia
+  int status;            // MS2_OK or MS2_ENONFINITE
+  long long steps_done, steps_target;
+  double dt, temperature;
+  double f_tr, f_rot;    // translational / rotational degrees of freedom
+  int sample_every, rdf_every, rdf_bins, rdf_due;
+  int acf_every, acf_origin_every, acf_nlag, acf_max_live;
+  int n_origins, rdf_ntp, pad0, pad1;
+  double rdf_rmax, rdf_inv_dr, rdf_reach2, u0;
+  double ekin_tr, ekin_rot;
+  double* r;             // Gear translation [5][3][n] (r, dt v, dt^2 a/2, ...); VV: r[0]
+  double* q;             // Gear quaternion  [5][4][n]
+  double* w;             // Gear body angular velocity [5][3][n]
+  double* vel;           // velocities [3][n] (VV state; Gear: r1/dt for the samplers)
+  double* moments;       // [kNumMoments]
+  unsigned long long* rdf;  // [rdf_ntp][rdf_bins] counts
+  double* acf_v;         // [acf_nlag]
+  double* acf_j;         // [acf_nlag]
+  double* acf_cnt;       // [acf_nlag]
+  double* origin_v;      // [acf_max_live][3][n]
+  double* origin_j;      // [acf_max_live][3]
+  long long* origin_t0;  // [acf_max_live]
 };
 
 

@@ -206,22 +206,30 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
   if (tid == 0) sd.kred[(size_t)kc * sd.mtiles + blockIdx.x] = s_red[0];
 }
 
-__global__ __launch_bounds__(256) void reduce_kspace_kernel(const SlotDev* __restrict__ slots,
+__global__ __launch_bounds__(256) void reduce_kforce_kernel(const SlotDev* __restrict__ slots,
                                                             const SysParams* __restrict__ prm) {
+  const SlotDev& sd = slots[blockIdx.y];
+  const SysParams& P = prm[blockIdx.y];
+  if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= sd.n) return;
+  const int np = sd.npad, ld = sd.com_ld;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int kc = 0; kc < sd.kchunks; ++kc)
+    for (int c = 0; c < 6; ++c) v[c] += sd.fk[((size_t)kc * 6 + c) * np + i];
+  for (int c = 0; c < 3; ++c) {
+    sd.force[c * ld + i] += v[c];
+    sd.torque[c * ld + i] += v[3 + c];
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_ksums_kernel(const SlotDev* __restrict__ slots,
+                                                           const SysParams* __restrict__ prm) {
   __shared__ double s_d[256];
   const SlotDev& sd = slots[blockIdx.x];
   const SysParams& P = prm[blockIdx.x];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
-  const int tid = threadIdx.x, np = sd.npad, ld = sd.com_ld;
-  for (int i = tid; i < sd.n; i += 256) {
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int kc = 0; kc < sd.kchunks; ++kc)
-      for (int c = 0; c < 6; ++c) v[c] += sd.fk[((size_t)kc * 6 + c) * np + i];
-    for (int c = 0; c < 3; ++c) {
-      sd.force[c * ld + i] += v[c];
-      sd.torque[c * ld + i] += v[3 + c];
-    }
-  }
+  const int tid = threadIdx.x;
   const int nr = sd.kchunks * sd.mtiles;
   const int per = (nr + 255) / 256;
   double d = 0.0;
@@ -248,7 +256,9 @@ hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const Speci
   hipLaunchKernelGGL(sk_reduce_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
-  hipLaunchKernelGGL(reduce_kspace_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
+  hipLaunchKernelGGL(reduce_kforce_kernel, dim3((64 * max_mtiles + 255) / 256, nslots), dim3(256), 0,
+                     st, slots, prm);
+  hipLaunchKernelGGL(reduce_ksums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();
 }
 

@@ -1,4 +1,524 @@
-// Device-resident MD step kernels (filled in with the batched path).
+// Device-resident MD step for many independent systems (slots) at once:
+// integrators, isokinetic thermostat and the on-the-fly samplers.
+//
+//   md_wrap_kernel     wrap the uploaded centres into [0, L)
+//   md_init_kernel     Gear start-up derivatives from the first force
+//                      evaluation; kinetic energies; ACF sample at t = 0
+//   md_begin_kernel    Gear predictor (Pascal triangle) and unit-quaternion
+//                      projection, or the first velocity-Verlet kick + drift
+//   md_end_kernel      Gear corrector (5-value coefficients for second-order
+//                      translation and first-order quaternion/Euler systems),
+//                      or the second kick; isokinetic rescaling; Lustig moment
+//                      sums (the paper's Sec. 3, Eq. 1 needs averages of U,
+//                      dU/dV, d2U/dV2 and their products); velocity and
+//                      electric-current autocorrelation on the extended time
+//                      step (Sec. 4; Sec. 5, Eqs. 3-4)
+//   rdf_kernel         site-site radial distribution histogram between LJ
+//                      sites (Sec. 5, Eq. 2), FP64 distances, integer counts
+// The O(N) kernels use one 1024-thread block per slot so that every
+// reduction (kinetic energy, ACF dot products) is a fixed in-block tree.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+
+namespace ms2 {
+
+__device__ __forceinline__ void qrot(double w, double x, double y, double z, double A[3][3]) {
+  A[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  A[0][1] = 2.0 * (x * y - w * z);
+  A[0][2] = 2.0 * (x * z + w * y);
+  A[1][0] = 2.0 * (x * y + w * z);
+  A[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  A[1][2] = 2.0 * (y * z - w * x);
+  A[2][0] = 2.0 * (x * z - w * y);
+  A[2][1] = 2.0 * (y * z + w * x);
+  A[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// d/dt of the quaternion for a body-frame angular velocity: (1/2) q (x) (0, w)
+__device__ __forceinline__ void quat_rate(const double* q, const double* w, double* out) {
+  out[0] = 0.5 * (-q[1] * w[0] - q[2] * w[1] - q[3] * w[2]);
+  out[1] = 0.5 * (q[0] * w[0] + q[2] * w[2] - q[3] * w[1]);
+  out[2] = 0.5 * (q[0] * w[1] - q[1] * w[2] + q[3] * w[0]);
+  out[3] = 0.5 * (q[0] * w[2] + q[1] * w[1] - q[2] * w[0]);
+}
+
+// Euler's equations in the principal frame; a zero moment freezes its axis
+__device__ __forceinline__ void euler_rate(const double* I, const double* tb, const double* w,
+                                           double* wd) {
+  wd[0] = I[0] > 0.0 ? (tb[0] + (I[1] - I[2]) * w[1] * w[2]) / I[0] : 0.0;
+  wd[1] = I[1] > 0.0 ? (tb[1] + (I[2] - I[0]) * w[2] * w[0]) / I[1] : 0.0;
+  wd[2] = I[2] > 0.0 ? (tb[2] + (I[0] - I[1]) * w[0] * w[1]) / I[2] : 0.0;
+}
+
+// body-frame torque A^T tau
+__device__ __forceinline__ void body_torque(const double A[3][3], const double* t, double* tb) {
+  for (int k = 0; k < 3; ++k) tb[k] = A[0][k] * t[0] + A[1][k] * t[1] + A[2][k] * t[2];
+}
+
+__device__ __forceinline__ double wrap(double x, double L, double invL) {
+  return x - L * floor(x * invL);
+}
+
+// block-wide fixed-order sum over kMdThreads threads
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int h = kMdThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// wraps the uploaded centres of one slot into [0, L)
+__global__ __launch_bounds__(256) void md_wrap_kernel(MDDev* md, const SysParams* prm, int slot, int n) {
+  const MDDev& m = md[slot];
+  const SysParams& P = prm[slot];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < 3; ++c) m.r[c * n + i] = wrap(m.r[c * n + i], P.L, P.invL);
+}
+
+// ACF sample at the current state: v is [3][npad]
+__device__ void acf_sample(MDDev& m, const SpeciesTable* tab, const SlotDev& sd, const double* v,
+                           int npad, long long s, double* red) {
+  const int tid = threadIdx.x, n = sd.n;
+  double jl[3] = {0, 0, 0};
+  for (int i = tid; i < n; i += kMdThreads) {
+    const double q = tab->sp[clamp_species(sd.species[i], tab->nsp)].net_charge;
+    for (int c = 0; c < 3; ++c) jl[c] += q * v[c * npad + i];
+  }
+  double j[3];
+  for (int c = 0; c < 3; ++c) j[c] = block_sum(jl[c], red);
+  if (s % m.acf_origin_every == 0) {
+    const int slot_o = m.n_origins % m.acf_max_live;
+    double* ov = m.origin_v + (size_t)slot_o * 3 * npad;
+    for (int i = tid; i < n; i += kMdThreads)
+      for (int c = 0; c < 3; ++c) ov[c * npad + i] = v[c * npad + i];
+    if (tid == 0) {
+      m.origin_t0[slot_o] = s;
+      for (int c = 0; c < 3; ++c) m.origin_j[3 * slot_o + c] = j[c];
+    }
+    __syncthreads();
+    if (tid == 0) m.n_origins += 1;
+    __syncthreads();
+  }
+  const int live = m.n_origins < m.acf_max_live ? m.n_origins : m.acf_max_live;
+  for (int o = 0; o < live; ++o) {
+    const long long t0 = m.origin_t0[o];
+    if (s < t0) continue;
+    const long long lag = (s - t0) / m.acf_every;
+    if (lag >= m.acf_nlag) continue;
+    const double* ov = m.origin_v + (size_t)o * 3 * npad;
+    double d = 0.0;
+    for (int i = tid; i < n; i += kMdThreads)
+      for (int c = 0; c < 3; ++c) d += ov[c * npad + i] * v[c * npad + i];
+    d = block_sum(d, red);
+    if (tid == 0) {
+      m.acf_v[lag] += d / n;
+      m.acf_j[lag] += m.origin_j[3 * o] * j[0] + m.origin_j[3 * o + 1] * j[1] +
+                      m.origin_j[3 * o + 2] * j[2];
+      m.acf_cnt[lag] += 1.0;
+    }
+  }
+}
+
+// translational and rotational kinetic sums: sum m v^2, sum I w^2
+__device__ void kinetic(const MDDev& m, const SpeciesTable* tab, const SlotDev& sd, const double* v,
+                        int npad, double* red, double& k2, double& kr2) {
+  const int tid = threadIdx.x, n = sd.n;
+  double a = 0.0, b = 0.0;
+  for (int i = tid; i < n; i += kMdThreads) {
+    const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
+    for (int c = 0; c < 3; ++c) {
+      a += D.mass * v[c * npad + i] * v[c * npad + i];
+      if (m.rotating) b += D.inertia[c] * m.w[c * npad + i] * m.w[c * npad + i];
+    }
+  }
+  k2 = block_sum(a, red);
+  kr2 = block_sum(b, red);
+}
+
+// one block per slot, launched for a single slot after its first force evaluation
+__global__ __launch_bounds__(kMdThreads) void md_init_kernel(SlotDev* slots, MDDev* md,
+                                                             const SpeciesTable* __restrict__ tab,
+                                                             int slot) {
+  __shared__ double red[kMdThreads];
+  SlotDev& sd = slots[slot];
+  MDDev& m = md[slot];
+  const int tid = threadIdx.x, n = sd.n, np = sd.com_ld;
+  const double dt = m.dt;
+  double* vnow;
+  if (m.integrator == MS2_GEAR) {
+    // r1 holds the uploaded velocity; w0 the uploaded body angular velocity
+    for (int i = tid; i < n; i += kMdThreads) {
+      const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
+      for (int c = 0; c < 3; ++c) {
+        const double v = m.r[(1 * 3 + c) * np + i];
+        m.r[(1 * 3 + c) * np + i] = dt * v;
+        m.r[(2 * 3 + c) * np + i] = 0.5 * dt * dt * sd.force[c * sd.com_ld + i] / D.mass;
+        m.r[(3 * 3 + c) * np + i] = 0.0;
+        m.r[(4 * 3 + c) * np + i] = 0.0;
+        if (m.vel) m.vel[c * np + i] = v;
+      }
+      if (m.rotating) {
+        double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
+        for (int c = 0; c < 4; ++c) q[c] = m.q[c * np + i];
+        for (int c = 0; c < 3; ++c) {
+          w[c] = m.w[c * np + i];
+          tq[c] = sd.torque[c * sd.com_ld + i];
+        }
+        qrot(q[0], q[1], q[2], q[3], A);
+        body_torque(A, tq, tb);
+        euler_rate(D.inertia, tb, w, wd);
+        quat_rate(q, w, qd);
+        for (int c = 0; c < 3; ++c) {
+          m.w[(1 * 3 + c) * np + i] = dt * wd[c];
+          m.w[(2 * 3 + c) * np + i] = 0.0;
+          m.w[(3 * 3 + c) * np + i] = 0.0;
+          m.w[(4 * 3 + c) * np + i] = 0.0;
+        }
+        for (int c = 0; c < 4; ++c) {
+          m.q[(1 * 4 + c) * np + i] = dt * qd[c];
+          m.q[(2 * 4 + c) * np + i] = 0.0;
+          m.q[(3 * 4 + c) * np + i] = 0.0;
+          m.q[(4 * 4 + c) * np + i] = 0.0;
+        }
+      }
+    }
+    vnow = m.vel;   // scratch copy of the velocities for the samplers
+  } else {
+    vnow = m.vel;
+  }
+  __syncthreads();
+  double k2, kr2;
+  kinetic(m, tab, sd, vnow, np, red, k2, kr2);
+  if (tid == 0) {
+    m.ekin_tr = 0.5 * k2;
+    m.ekin_rot = 0.5 * kr2;
+  }
+  if (m.acf_every > 0) acf_sample(m, tab, sd, vnow, np, 0, red);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict__ slots, MDDev* md,
+                                                       const SysParams* __restrict__ prm,
+                                                       const SpeciesTable* __restrict__ tab) {
+  const SlotDev& sd = slots[blockIdx.y];
+  const MDDev& m = md[blockIdx.y];
+  if (!m.active) return;
+  const SysParams& P = prm[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= sd.n) return;
+  const int np = sd.com_ld;
+  if (m.integrator == MS2_GEAR) {
+    for (int c = 0; c < 3; ++c) {
+      double y0 = m.r[(0 * 3 + c) * np + i], y1 = m.r[(1 * 3 + c) * np + i],
+             y2 = m.r[(2 * 3 + c) * np + i], y3 = m.r[(3 * 3 + c) * np + i],
+             y4 = m.r[(4 * 3 + c) * np + i];
+      m.r[(0 * 3 + c) * np + i] = y0 + y1 + y2 + y3 + y4;
+      m.r[(1 * 3 + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
+      m.r[(2 * 3 + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
+      m.r[(3 * 3 + c) * np + i] = y3 + 4.0 * y4;
+    }
+    if (m.rotating) {
+      for (int c = 0; c < 3; ++c) {
+        double y0 = m.w[(0 * 3 + c) * np + i], y1 = m.w[(1 * 3 + c) * np + i],
+               y2 = m.w[(2 * 3 + c) * np + i], y3 = m.w[(3 * 3 + c) * np + i],
+               y4 = m.w[(4 * 3 + c) * np + i];
+        m.w[(0 * 3 + c) * np + i] = y0 + y1 + y2 + y3 + y4;
+        m.w[(1 * 3 + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
+        m.w[(2 * 3 + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
+        m.w[(3 * 3 + c) * np + i] = y3 + 4.0 * y4;
+      }
+      double q0[4];
+      for (int c = 0; c < 4; ++c) {
+        double y0 = m.q[(0 * 4 + c) * np + i], y1 = m.q[(1 * 4 + c) * np + i],
+               y2 = m.q[(2 * 4 + c) * np + i], y3 = m.q[(3 * 4 + c) * np + i],
+               y4 = m.q[(4 * 4 + c) * np + i];
+        q0[c] = y0 + y1 + y2 + y3 + y4;
+        m.q[(1 * 4 + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
+        m.q[(2 * 4 + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
+        m.q[(3 * 4 + c) * np + i] = y3 + 4.0 * y4;
+      }
+      // the force evaluation uses the predicted orientation projected onto |q| = 1
+      const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+      for (int c = 0; c < 4; ++c) m.q[c * np + i] = q0[c] / nq;
+    }
+  } else {
+    const double h = 0.5 * m.dt / tab->sp[clamp_species(sd.species[i], tab->nsp)].mass;
+    for (int c = 0; c < 3; ++c) {
+      const double v = m.vel[c * np + i] + h * sd.force[c * sd.com_ld + i];
+      m.vel[c * np + i] = v;
+      m.r[c * np + i] = wrap(m.r[c * np + i] + m.dt * v, P.L, P.invL);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDev* md,
+                                                            const SysParams* __restrict__ prm,
+                                                            const SpeciesTable* __restrict__ tab) {
+  __shared__ double red[kMdThreads];
+  SlotDev& sd = slots[blockIdx.x];
+  MDDev& m = md[blockIdx.x];
+  if (!m.active) return;
+  const SysParams& P = prm[blockIdx.x];
+  const int tid = threadIdx.x, n = sd.n, np = sd.com_ld, ld = sd.com_ld;
+  const double dt = m.dt;
+  const double ct[5] = {19.0 / 120.0, 3.0 / 4.0, 1.0, 1.0 / 2.0, 1.0 / 12.0};
+  const double cr[5] = {251.0 / 720.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0};
+  double* v = m.vel;
+  for (int i = tid; i < n; i += kMdThreads) {
+    const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
+    if (m.integrator == MS2_GEAR) {
+      for (int c = 0; c < 3; ++c) {
+        const double delta = 0.5 * dt * dt * sd.force[c * ld + i] / D.mass - m.r[(2 * 3 + c) * np + i];
+        for (int d = 0; d < 5; ++d) m.r[(d * 3 + c) * np + i] += ct[d] * delta;
+      }
+      if (m.rotating) {
+        double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
+        for (int c = 0; c < 4; ++c) q[c] = m.q[c * np + i];
+        for (int c = 0; c < 3; ++c) {
+          w[c] = m.w[c * np + i];
+          tq[c] = sd.torque[c * ld + i];
+        }
+        qrot(q[0], q[1], q[2], q[3], A);
+        body_torque(A, tq, tb);
+        euler_rate(D.inertia, tb, w, wd);
+        quat_rate(q, w, qd);
+        for (int c = 0; c < 3; ++c) {
+          const double delta = dt * wd[c] - m.w[(1 * 3 + c) * np + i];
+          for (int d = 0; d < 5; ++d) m.w[(d * 3 + c) * np + i] += cr[d] * delta;
+        }
+        double q0[4];
+        for (int c = 0; c < 4; ++c) {
+          const double delta = dt * qd[c] - m.q[(1 * 4 + c) * np + i];
+          for (int d = 0; d < 5; ++d) m.q[(d * 4 + c) * np + i] += cr[d] * delta;
+          q0[c] = m.q[c * np + i];
+        }
+        const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+        for (int c = 0; c < 4; ++c) m.q[c * np + i] = q0[c] / nq;
+      }
+      for (int c = 0; c < 3; ++c) {
+        m.r[c * np + i] = wrap(m.r[c * np + i], P.L, P.invL);
+        v[c * np + i] = m.r[(1 * 3 + c) * np + i] / dt;
+      }
+    } else {
+      const double h = 0.5 * dt / D.mass;
+      for (int c = 0; c < 3; ++c) v[c * np + i] += h * sd.force[c * ld + i];
+    }
+  }
+  __syncthreads();
+  double k2, kr2;
+  kinetic(m, tab, sd, v, np, red, k2, kr2);
+  if (m.temperature > 0.0) {
+    const double ft = sqrt(m.temperature * m.f_tr / k2);
+    const double fr = (m.f_rot > 0.0 && kr2 > 0.0) ? sqrt(m.temperature * m.f_rot / kr2) : 1.0;
+    for (int i = tid; i < n; i += kMdThreads) {
+      for (int c = 0; c < 3; ++c) {
+        v[c * np + i] *= ft;
+        if (m.integrator == MS2_GEAR) m.r[(1 * 3 + c) * np + i] *= ft;
+      }
+      if (m.rotating && fr != 1.0) {
+        for (int c = 0; c < 3; ++c) m.w[c * np + i] *= fr;
+        for (int c = 0; c < 4; ++c) m.q[(1 * 4 + c) * np + i] *= fr;
+      }
+    }
+    k2 *= ft * ft;
+    kr2 *= fr * fr;
+    __syncthreads();
+  }
+  const long long s = m.steps_done + 1;
+  if (tid == 0) {
+    m.ekin_tr = 0.5 * k2;
+    m.ekin_rot = 0.5 * kr2;
+    const double* su = sd.sums;
+    const double U = su[MS2_SUM_U_LJ] + su[MS2_SUM_U_ELEC] + su[MS2_SUM_U_RECIP] + su[MS2_SUM_U_CONST] +
+                     su[MS2_SUM_U_LRC];
+    bool ok = isfinite(U) && isfinite(k2) && isfinite(su[MS2_SUM_VIRIAL]);
+    if (m.sample_every > 0 && s % m.sample_every == 0) {
+      const double X = U - m.u0;
+      const double us = su[MS2_SUM_US] + su[MS2_SUM_US_LRC];
+      const double uss = su[MS2_SUM_USS] + su[MS2_SUM_USS_LRC];
+      const double Y = us / (3.0 * P.V);
+      const double Z = (uss - 2.0 * us) / (9.0 * P.V * P.V);
+      double* mo = m.moments;
+      mo[0] += 1.0;
+      mo[1] += X;
+      mo[2] += X * X;
+      mo[3] += X * X * X;
+      mo[4] += Y;
+      mo[5] += X * Y;
+      mo[6] += X * X * Y;
+      mo[7] += Y * Y;
+      mo[8] += X * Y * Y;
+      mo[9] += Z;
+      mo[10] += X * Z;
+    }
+    m.rdf_due = (m.rdf_every > 0 && s % m.rdf_every == 0) ? 1 : 0;
+    if (!ok) m.status = MS2_ENONFINITE;
+  }
+  if (m.acf_every > 0 && s % m.acf_every == 0) acf_sample(m, tab, sd, v, np, s, red);
+  __syncthreads();
+  if (tid == 0) {
+    m.steps_done = s;
+    if (s >= m.steps_target || m.status != MS2_OK) {
+      m.active = 0;
+      sd.active = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// RDF: the pair kernel's work items; only pairs with j > i count.
+// ---------------------------------------------------------------------------
+constexpr int kRdfLj = 4;   // LJ sites per species in the largest model class
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void rdf_kernel(const WorkItem* __restrict__ items, int item_base,
+                                                     const SlotDev* __restrict__ slots,
+                                                     const MDDev* __restrict__ md,
+                                                     const SysParams* __restrict__ prm,
+                                                     const SpeciesTable* __restrict__ tab) {
+  constexpr int TJ = 64 * W;
+  constexpr int kLds = W == 4 ? 4096 : 8192;
+  __shared__ double s_com[3][TJ];
+  __shared__ double s_lj[kRdfLj][3][TJ];
+  __shared__ int s_sp[TJ];
+  __shared__ unsigned int s_hist[kLds];
+  const WorkItem it = items[item_base + blockIdx.x];
+  const SlotDev& sd = slots[it.slot];
+  const MDDev& m = md[it.slot];
+  if (!m.rdf_due) return;
+  const SysParams& P = prm[it.slot];
+  const int tid = threadIdx.x, n = sd.n, ld = sd.com_ld, nsp = tab->nsp;
+  const int bins = m.rdf_bins, T = tab->n_lj_types;
+  const bool use_lds = m.rdf_ntp * bins <= kLds;
+  if (use_lds)
+    for (int e = tid; e < m.rdf_ntp * bins; e += TJ) s_hist[e] = 0u;
+  const int i = it.i0 + tid;
+  const bool iv = i < n;
+  const int ic = iv ? i : 0;
+  const int spi = clamp_species(sd.species[ic], nsp);
+  const SpeciesDev& Di = tab->sp[spi];
+  double A[3][3];
+  qrot(sd.quat[ic], sd.quat[ld + ic], sd.quat[2 * ld + ic], sd.quat[3 * ld + ic], A);
+  double di[kRdfLj][3];
+#pragma unroll
+  for (int a = 0; a < kRdfLj; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      di[a][c] = a < Di.nlj ? A[c][0] * Di.lj_pos[a][0] + A[c][1] * Di.lj_pos[a][1] +
+                                  A[c][2] * Di.lj_pos[a][2]
+                            : 0.0;
+  const double xi = sd.com[ic], yi = sd.com[ld + ic], zi = sd.com[2 * ld + ic];
+  unsigned long long* ghist = m.rdf;
+  for (int jt = it.j0; jt < it.j1; jt += TJ) {
+    __syncthreads();
+    {
+      const int j = jt + tid;
+      const bool jv = j < it.j1 && j < n;
+      const int jc = jv ? j : 0;
+      const int spj = clamp_species(sd.species[jc], nsp);
+      const SpeciesDev& Dj = tab->sp[spj];
+      double B[3][3];
+      qrot(sd.quat[jc], sd.quat[ld + jc], sd.quat[2 * ld + jc], sd.quat[3 * ld + jc], B);
+      s_com[0][tid] = sd.com[jc];
+      s_com[1][tid] = sd.com[ld + jc];
+      s_com[2][tid] = sd.com[2 * ld + jc];
+      s_sp[tid] = jv ? spj : -1;
+      for (int a = 0; a < kRdfLj; ++a)
+        for (int c = 0; c < 3; ++c)
+          s_lj[a][c][tid] = a < Dj.nlj ? B[c][0] * Dj.lj_pos[a][0] + B[c][1] * Dj.lj_pos[a][1] +
+                                             B[c][2] * Dj.lj_pos[a][2]
+                                       : 0.0;
+    }
+    __syncthreads();
+    if (!iv) continue;
+    for (int jj = 0; jj < TJ; ++jj) {
+      const int j = jt + jj;
+      const int spj = s_sp[jj];
+      if (spj < 0 || j <= i) continue;
+      double R[3];
+      {
+#pragma clang fp contract(off)
+        const double dx = xi - s_com[0][jj], dy = yi - s_com[1][jj], dz = zi - s_com[2][jj];
+        R[0] = dx - P.L * rint(dx * P.invL);
+        R[1] = dy - P.L * rint(dy * P.invL);
+        R[2] = dz - P.L * rint(dz * P.invL);
+      }
+      if (R[0] * R[0] + R[1] * R[1] + R[2] * R[2] >= m.rdf_reach2) continue;
+      const SpeciesDev& Dj = tab->sp[spj];
+#pragma unroll
+      for (int a = 0; a < kRdfLj; ++a) {
+        if (a >= Di.nlj) break;
+        for (int b = 0; b < Dj.nlj; ++b) {
+          double r;
+          {
+#pragma clang fp contract(off)
+            const double rx = R[0] + di[a][0] - s_lj[b][0][jj];
+            const double ry = R[1] + di[a][1] - s_lj[b][1][jj];
+            const double rz = R[2] + di[a][2] - s_lj[b][2][jj];
+            r = sqrt(rx * rx + ry * ry + rz * rz);
+          }
+          if (!(r < m.rdf_rmax)) continue;
+          const int bin = (int)(r * m.rdf_inv_dr);
+          if (bin >= bins) continue;
+          int t1 = Di.lj_type0 + a, t2 = Dj.lj_type0 + b;
+          if (t1 > t2) { const int x = t1; t1 = t2; t2 = x; }
+          const int tp = t1 * T - t1 * (t1 - 1) / 2 + (t2 - t1);
+          if (use_lds)
+            atomicAdd(&s_hist[tp * bins + bin], 1u);
+          else
+            atomicAdd(&ghist[(size_t)tp * bins + bin], 1ull);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (use_lds)
+    for (int e = tid; e < m.rdf_ntp * bins; e += TJ)
+      if (s_hist[e]) atomicAdd(&ghist[e], (unsigned long long)s_hist[e]);
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_md_wrap(MDDev* md, const SysParams* prm, int slot, int n, hipStream_t st) {
+  hipLaunchKernelGGL(md_wrap_kernel, dim3((n + 255) / 256), dim3(256), 0, st, md, prm, slot, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_init(SlotDev* slots, MDDev* md, const SpeciesTable* tab, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(md_init_kernel, dim3(1), dim3(kMdThreads), 0, st, slots, md, tab, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_begin(const SlotDev* slots, MDDev* md, const SysParams* prm,
+                           const SpeciesTable* tab, int nslots, int max_n, hipStream_t st) {
+  hipLaunchKernelGGL(md_begin_kernel, dim3((max_n + 255) / 256, nslots), dim3(256), 0, st, slots, md,
+                     prm, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const SpeciesTable* tab,
+                         int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(md_end_kernel, dim3(nslots), dim3(kMdThreads), 0, st, slots, md, prm, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_rdf(int waves, const WorkItem* items, int base, int count, const SlotDev* slots,
+                      const MDDev* md, const SysParams* prm, const SpeciesTable* tab, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (waves == 4)
+    hipLaunchKernelGGL(rdf_kernel<4>, dim3(count), dim3(256), 0, st, items, base, slots, md, prm, tab);
+  else
+    hipLaunchKernelGGL(rdf_kernel<1>, dim3(count), dim3(64), 0, st, items, base, slots, md, prm, tab);
+  return hipGetLastError();
+}
+
+}  // namespace ms2

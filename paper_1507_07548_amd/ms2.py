@@ -207,3 +207,103 @@ def evaluate(ctx: Context, system, precision: int = FP64, dev: Optional[DeviceSy
         ctx.ewald_kspace(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums, stream)
     torch.cuda.synchronize()
     return d.force.cpu().numpy().T.copy(), d.torque.cpu().numpy().T.copy(), d.sums.cpu().numpy().copy()
+
+
+def system_struct(system, precision: int, n_steps: Optional[int] = None):
+    """Marshal an inputs.System (+ its MDSettings) into ms2_system.  Returns
+    (struct, keep-alive host arrays)."""
+    md = system.md
+    sp = np.ascontiguousarray(system.species_idx, dtype=np.int32)
+    com = np.ascontiguousarray(system.com.T, dtype=np.float64)
+    quat = np.ascontiguousarray(system.quat.T, dtype=np.float64)
+    vel = np.ascontiguousarray(system.vel.T, dtype=np.float64)
+    om = np.ascontiguousarray(system.omega.T, dtype=np.float64)
+    keep = (sp, com, quat, vel, om)
+    dp = lambda a: a.ctypes.data_as(P(c_double))
+    s = System(params=params_struct(system.params, precision), n_mol=system.n, integrator=md.integrator,
+               n_steps=md.n_steps if n_steps is None else n_steps, dt=md.dt, temperature=md.temperature,
+               sample_every=md.sample_every, rdf_every=md.rdf_every, rdf_bins=md.rdf_bins,
+               acf_every=md.acf_every, acf_origin_every=md.acf_origin_every, acf_nlag=md.acf_nlag,
+               rdf_rmax=md.rdf_rmax, u0=md.u0, h_species=sp.ctypes.data_as(P(c_int32)), h_com=dp(com),
+               h_quat=dp(quat), h_vel=dp(vel), h_omega=dp(om))
+    return s, keep
+
+
+class Batch:
+    """ms2_batch: device-resident slots advanced together by ms2_step."""
+
+    def __init__(self, ctx: Context, max_slots: int, hbm_budget: int = 0):
+        self.ctx = ctx
+        h = c_void_p()
+        check(lib().ms2_batch_create(ctx.handle, max_slots, hbm_budget, ctypes.byref(h)))
+        self.handle = h
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().ms2_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self, system, precision: int) -> int:
+        s, keep = system_struct(system, precision)
+        b = c_size_t()
+        check(lib().ms2_slot_footprint(self.ctx.handle, ctypes.byref(s), ctypes.byref(b)))
+        return b.value
+
+    def admit(self, system, precision: int, n_steps: Optional[int] = None, stream=None) -> int:
+        s, keep = system_struct(system, precision, n_steps)
+        slot = c_int32()
+        check(lib().ms2_slot_admit(self.handle, ctypes.byref(s), ctypes.byref(slot), _stream_ptr(stream)))
+        self.shapes[slot.value] = (system.n, system.md.rdf_bins, max(system.md.acf_nlag, 0),
+                                   len(system.species))
+        return slot.value
+
+    def retire(self, slot: int):
+        check(lib().ms2_slot_retire(self.handle, slot))
+        self.shapes.pop(slot, None)
+
+    def step(self, n_steps: int, graph: bool = True, stream=None):
+        check(lib().ms2_step(self.handle, n_steps, STEP_GRAPH if graph else 0, _stream_ptr(stream)))
+
+    def status(self, slot: int, stream=None):
+        steps, st = c_int64(), c_int32()
+        check(lib().ms2_slot_status(self.handle, slot, ctypes.byref(steps), ctypes.byref(st),
+                                    _stream_ptr(stream)))
+        return steps.value, st.value
+
+    def sample(self, slot: int, state: bool = True, stream=None) -> dict:
+        n, bins, nlag, _ = self.shapes[slot]
+        out = Samples()
+        arrays = {}
+
+        def buf(name, shape):
+            a = np.zeros(shape, dtype=np.float64)
+            arrays[name] = a
+            setattr(out, "h_" + name, a.ctypes.data_as(P(c_double)))
+
+        T = sum(1 for s in self.ctx.species for site in s.sites if site.kind == 0)
+        if bins:
+            buf("rdf", (T * (T + 1) // 2, bins))
+        if nlag:
+            buf("acf_v", nlag)
+            buf("acf_j", nlag)
+            buf("acf_cnt", nlag)
+        if state:
+            buf("com", (3, n))
+            buf("quat", (4, n))
+            buf("vel", (3, n))
+            buf("omega", (3, n))
+            buf("force", (3, n))
+            buf("torque", (3, n))
+        check(lib().ms2_sample(self.handle, slot, ctypes.byref(out), _stream_ptr(stream)))
+        res = {"steps_done": out.steps_done, "status": out.status, "sums": np.array(out.sums[:]),
+               "ekin_trans": out.ekin_trans, "ekin_rot": out.ekin_rot, "moments": np.array(out.moments[:])}
+        for k, v in arrays.items():
+            res[k] = v.T.copy() if k in ("com", "quat", "vel", "omega", "force", "torque") else v
+        return res
