@@ -173,9 +173,16 @@ typedef struct {
   const double* h_omega;     /* [3][n] body frame */
 } ms2_system;
 
+/* Batch flags */
+enum {
+  MS2_BATCH_PLAIN_TILES = 1  /* tile shapes of the one-system-per-launch path
+                                (many small work items per system) instead of
+                                the batched shapes (fewer, larger items)      */
+};
+
 /* Creates a batch of at most max_slots concurrently resident systems whose
  * device state may use at most hbm_budget bytes (0 = no limit). */
-ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget,
+ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget, int32_t flags,
                             ms2_batch** out);
 void ms2_batch_destroy(ms2_batch* batch);
 
@@ -194,7 +201,13 @@ ms2_status ms2_slot_admit(ms2_batch* batch, const ms2_system* h_sys, int32_t* sl
 ms2_status ms2_slot_retire(ms2_batch* batch, int32_t slot);
 
 /* Step flags */
-enum { MS2_STEP_GRAPH = 1 };   /* capture the n_steps launches in a hipGraph and replay it */
+enum {
+  MS2_STEP_GRAPH = 1,   /* capture the n_steps launches in a hipGraph and replay it */
+  MS2_STEP_TIMING = 2,  /* record HIP events around the pair-kernel launches of
+                           every step (inside the graph when captured)       */
+  MS2_STEP_PREPARE = 4  /* with MS2_STEP_GRAPH: capture and instantiate the
+                           graph for these n_steps and flags, run nothing    */
+};
 
 /* Advances every active slot by up to n_steps MD steps on the device: per
  * step a predictor (Gear) or drift (VV), the force path of ms2_forces and
@@ -204,6 +217,11 @@ enum { MS2_STEP_GRAPH = 1 };   /* capture the n_steps launches in a hipGraph and
  * Asynchronous; nothing is copied to the host. */
 ms2_status ms2_step(ms2_batch* batch, int32_t n_steps, int32_t flags, void* stream);
 
+/* Elapsed time of the pair-kernel launches of the last ms2_step call made
+ * with MS2_STEP_TIMING, summed over its steps (HIP events on that call's
+ * stream), and the number of steps timed.  Synchronizes that stream. */
+ms2_status ms2_batch_timing(ms2_batch* batch, double* pair_ms, int32_t* n_steps);
+
 /* Samples copied out of a slot (host memory owned by the caller). */
 typedef struct {
   int64_t steps_done;
@@ -211,6 +229,8 @@ typedef struct {
   int32_t rdf_ntypes;        /* LJ site types; histograms for t1 <= t2    */
   double sums[MS2_NSUM];     /* force-path sums of the last step          */
   double ekin_trans, ekin_rot;
+  double pairs_total;        /* accepted molecule pairs summed over all steps   */
+  double site_pairs_total;   /* interacting site pairs summed over all steps    */
   double moments[11];        /* sums of X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ
                                 (slot 0 = number of samples); X = U - u0,
                                 Y = dU/dV, Z = d2U/dV2                     */

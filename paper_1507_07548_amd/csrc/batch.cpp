@@ -62,7 +62,7 @@ struct SlotLayout {
 };
 
 struct SlotShape {
-  int n, npad, cls, precision, jsplits, nitems, waves, nk, kchunks, mchunks, mtiles;
+  int n, npad, cls, precision, jsplits, nitems, waves, mode, nk, kchunks, mchunks, mtiles;
   int rdf_ntp, rdf_bins, acf_nlag, acf_max_live;
 };
 
@@ -147,8 +147,12 @@ struct ms2_batch {
   bool any_ewald = false, any_rdf = false;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  int graph_steps = 0;
+  int graph_steps = 0, graph_flags = 0;
   hipStream_t last_stream = nullptr;
+  int flags = 0;
+  // pair-kernel timing events, one (begin, end) pair per step
+  std::vector<hipEvent_t> ev_begin, ev_end;
+  int timed_steps = 0;
 };
 
 namespace {
@@ -161,7 +165,7 @@ void drop_graph(ms2_batch* b) {
   b->graph_steps = 0;
 }
 
-ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, SlotShape& s) {
+ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s) {
   if (!sys) return set_error(MS2_EINVAL, "system is NULL");
   ms2_status st = check_params(ctx, &sys->params);
   if (st != MS2_OK) return st;
@@ -192,7 +196,8 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, SlotShape& s) {
   s.npad = (s.n + 63) & ~63;
   s.cls = ctx->cls;
   s.precision = sys->params.precision;
-  const TileCfg cfg = tile_config(ctx, 1, s.precision, s.n);
+  s.mode = mode;
+  const TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
   s.waves = cfg.waves;
   s.jsplits = (s.n + cfg.jchunk - 1) / cfg.jchunk;
   s.nitems = ((s.n + 64 * cfg.waves - 1) / (64 * cfg.waves)) * s.jsplits;
@@ -233,10 +238,7 @@ void rebuild_items(ms2_batch* b) {
       for (int s = 0; s < b->max_slots; ++s) {
         const SlotHost& h = b->slots[s];
         if (!h.used || h.shape.precision != prec || h.shape.waves != waves) continue;
-        TileCfg c;
-        c.waves = waves;
-        c.jchunk = (h.shape.n + h.shape.jsplits - 1) / h.shape.jsplits;
-        c.jchunk = tile_config(b->ctx, 1, prec, h.shape.n).jchunk;
+        const TileCfg c = tile_config(b->ctx, h.shape.mode, prec, h.shape.n);
         int js = 0;
         build_items(h.shape.n, c, s, all, &js);
       }
@@ -264,7 +266,7 @@ void rebuild_items(ms2_batch* b) {
 }
 
 // the force path for every slot of the batch (pair part + reduction + k-space)
-ms2_status enqueue_forces(ms2_batch* b, hipStream_t st) {
+ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
   ms2_ctx* ctx = b->ctx;
   const SlotDev* ds = (const SlotDev*)b->d_slots.p;
   const SysParams* dp = (const SysParams*)b->d_prm.p;
@@ -274,9 +276,11 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st) {
     for (auto& g : b->groups) any |= g.precision == prec;
     if (any) MS2_HIP(launch_site_frame(ctx->cls, prec, ds, dp, ctx->d_tab, b->max_slots, b->max_n, st));
   }
+  if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_begin[timed_step], st));
   for (auto& g : b->groups)
     MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, di, g.begin, g.end - g.begin, ds, dp, ctx->d_tab,
                         st));
+  if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
   MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
   if (b->any_ewald)
     MS2_HIP(launch_kspace(ds, dp, ctx->d_tab, b->max_slots, b->max_kblocks, b->max_mchunks,
@@ -284,13 +288,13 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st) {
   return MS2_OK;
 }
 
-ms2_status enqueue_step(ms2_batch* b, hipStream_t st) {
+ms2_status enqueue_step(ms2_batch* b, hipStream_t st, int timed_step) {
   ms2_ctx* ctx = b->ctx;
   SlotDev* ds = (SlotDev*)b->d_slots.p;
   MDDev* dm = (MDDev*)b->d_md.p;
   const SysParams* dp = (const SysParams*)b->d_prm.p;
   MS2_HIP(launch_md_begin(ds, dm, dp, ctx->d_tab, b->max_slots, b->max_n, st));
-  ms2_status s = enqueue_forces(b, st);
+  ms2_status s = enqueue_forces(b, st, timed_step);
   if (s != MS2_OK) return s;
   MS2_HIP(launch_md_end(ds, dm, dp, ctx->d_tab, b->max_slots, st));
   if (b->any_rdf)
@@ -304,7 +308,8 @@ ms2_status enqueue_step(ms2_batch* b, hipStream_t st) {
 
 extern "C" {
 
-ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget, ms2_batch** out) {
+ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget, int32_t flags,
+                            ms2_batch** out) {
   if (!out) return set_error(MS2_EINVAL, "out is NULL");
   *out = nullptr;
   if (!ctx || max_slots < 1 || max_slots > 65535) return set_error(MS2_EINVAL, "bad batch arguments");
@@ -313,6 +318,7 @@ ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget, 
   b->ctx = ctx;
   b->max_slots = max_slots;
   b->budget = hbm_budget;
+  b->flags = flags;
   b->slots.resize(max_slots);
   hipError_t e = b->d_slots.ensure(sizeof(SlotDev) * max_slots);
   if (e == hipSuccess) e = b->d_md.ensure(sizeof(MDDev) * max_slots);
@@ -341,6 +347,8 @@ void ms2_batch_destroy(ms2_batch* b) {
   (void)hipSetDevice(b->ctx->device);
   (void)hipDeviceSynchronize();
   drop_graph(b);
+  for (auto e : b->ev_begin) (void)hipEventDestroy(e);
+  for (auto e : b->ev_end) (void)hipEventDestroy(e);
   for (auto& s : b->slots) s.mem.release();
   b->d_slots.release();
   b->d_md.release();
@@ -352,7 +360,7 @@ void ms2_batch_destroy(ms2_batch* b) {
 ms2_status ms2_slot_footprint(ms2_ctx* ctx, const ms2_system* sys, size_t* bytes) {
   if (!ctx || !bytes) return set_error(MS2_EINVAL, "bad arguments");
   SlotShape s;
-  ms2_status st = shape_of(ctx, sys, s);
+  ms2_status st = shape_of(ctx, sys, 1, s);
   if (st != MS2_OK) return st;
   *bytes = layout_of(s).total;
   return MS2_OK;
@@ -363,7 +371,7 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   ms2_ctx* ctx = b->ctx;
   hipStream_t st = (hipStream_t)stream;
   SlotShape shape;
-  ms2_status s = shape_of(ctx, sys, shape);
+  ms2_status s = shape_of(ctx, sys, (b->flags & MS2_BATCH_PLAIN_TILES) ? 0 : 1, shape);
   if (s != MS2_OK) return s;
   int slot = -1;
   for (int k = 0; k < b->max_slots; ++k)
@@ -536,19 +544,31 @@ ms2_status ms2_step(ms2_batch* b, int32_t n_steps, int32_t flags, void* stream) 
   bool any = false;
   for (auto& s : b->slots) any |= s.used;
   if (!any) return MS2_OK;
+  const bool timing = (flags & MS2_STEP_TIMING) != 0;
+  if (timing) {
+    while ((int)b->ev_begin.size() < n_steps) {
+      hipEvent_t e0, e1;
+      MS2_HIP(hipEventCreate(&e0));
+      MS2_HIP(hipEventCreate(&e1));
+      b->ev_begin.push_back(e0);
+      b->ev_end.push_back(e1);
+    }
+    b->timed_steps = n_steps;
+  }
   const bool graph = (flags & MS2_STEP_GRAPH) && st != nullptr;
   if (!graph) {
     for (int k = 0; k < n_steps; ++k) {
-      ms2_status s = enqueue_step(b, st);
+      ms2_status s = enqueue_step(b, st, timing ? k : -1);
       if (s != MS2_OK) return s;
     }
     return MS2_OK;
   }
-  if (!b->exec || b->graph_steps != n_steps) {
+  const int gflags = flags & ~MS2_STEP_PREPARE;
+  if (!b->exec || b->graph_steps != n_steps || b->graph_flags != gflags) {
     drop_graph(b);
     MS2_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     ms2_status s = MS2_OK;
-    for (int k = 0; k < n_steps && s == MS2_OK; ++k) s = enqueue_step(b, st);
+    for (int k = 0; k < n_steps && s == MS2_OK; ++k) s = enqueue_step(b, st, timing ? k : -1);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (s != MS2_OK) {
@@ -559,8 +579,25 @@ ms2_status ms2_step(ms2_batch* b, int32_t n_steps, int32_t flags, void* stream) 
     b->graph = g;
     MS2_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->graph_steps = n_steps;
+    b->graph_flags = gflags;
   }
+  if (flags & MS2_STEP_PREPARE) return MS2_OK;
   MS2_HIP(hipGraphLaunch(b->exec, st));
+  return MS2_OK;
+}
+
+ms2_status ms2_batch_timing(ms2_batch* b, double* pair_ms, int32_t* n_steps) {
+  if (!b || !pair_ms) return set_error(MS2_EINVAL, "bad arguments");
+  MS2_HIP(hipSetDevice(b->ctx->device));
+  MS2_HIP(hipStreamSynchronize(b->last_stream));
+  double tot = 0.0;
+  for (int k = 0; k < b->timed_steps; ++k) {
+    float ms = 0.0f;
+    MS2_HIP(hipEventElapsedTime(&ms, b->ev_begin[k], b->ev_end[k]));
+    tot += ms;
+  }
+  *pair_ms = tot;
+  if (n_steps) *n_steps = b->timed_steps;
   return MS2_OK;
 }
 
@@ -613,6 +650,8 @@ ms2_status ms2_sample(ms2_batch* b, int32_t slot, ms2_samples* out, void* stream
   out->rdf_ntypes = b->ctx->tab.n_lj_types;
   out->ekin_trans = m.ekin_tr;
   out->ekin_rot = m.ekin_rot;
+  out->pairs_total = m.pairs_total;
+  out->site_pairs_total = m.site_pairs_total;
   return MS2_OK;
 }
 

@@ -131,6 +131,7 @@ struct MDDev {
   int n_origins, rdf_ntp, pad0, pad1;
   double rdf_rmax, rdf_inv_dr, rdf_reach2, u0;
   double ekin_tr, ekin_rot;
+  double pairs_total, site_pairs_total;
   double* r;             // Gear translation [5][3][n] (r, dt v, dt^2 a/2, ...); VV: r[0]
   double* q;             // Gear quaternion  [5][4][n]
   double* w;             // Gear body angular velocity [5][3][n]

@@ -339,6 +339,8 @@ __global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDe
     m.ekin_tr = 0.5 * k2;
     m.ekin_rot = 0.5 * kr2;
     const double* su = sd.sums;
+    m.pairs_total += su[MS2_SUM_NPAIR];
+    m.site_pairs_total += su[MS2_SUM_NSITE];
     const double U = su[MS2_SUM_U_LJ] + su[MS2_SUM_U_ELEC] + su[MS2_SUM_U_RECIP] + su[MS2_SUM_U_CONST] +
                      su[MS2_SUM_U_LRC];
     bool ok = isfinite(U) && isfinite(k2) && isfinite(su[MS2_SUM_VIRIAL]);

@@ -24,6 +24,9 @@ SUM_NAMES = ["u_lj", "u_elec", "u_recip", "u_const", "u_lrc", "virial", "us", "u
              "us_lrc", "uss_lrc", "npair", "nsite"]
 FP64, FP32 = 0, 1
 STEP_GRAPH = 1
+STEP_TIMING = 2
+STEP_PREPARE = 4
+BATCH_PLAIN_TILES = 1
 STATUS = {0: "MS2_OK", 1: "MS2_EINVAL", 2: "MS2_ENOMEM", 3: "MS2_EDEVICE", 4: "MS2_ENONFINITE",
           5: "MS2_EFULL"}
 
@@ -57,7 +60,7 @@ class System(ctypes.Structure):
 class Samples(ctypes.Structure):
     _fields_ = [("steps_done", c_int64), ("status", c_int32), ("rdf_ntypes", c_int32),
                 ("sums", c_double * NSUM), ("ekin_trans", c_double), ("ekin_rot", c_double),
-                ("moments", c_double * 11), ("h_rdf", P(c_double)), ("h_acf_v", P(c_double)),
+                ("pairs_total", c_double), ("site_pairs_total", c_double), ("moments", c_double * 11), ("h_rdf", P(c_double)), ("h_acf_v", P(c_double)),
                 ("h_acf_j", P(c_double)), ("h_acf_cnt", P(c_double)), ("h_com", P(c_double)),
                 ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double)),
                 ("h_force", P(c_double)), ("h_torque", P(c_double))]
@@ -73,7 +76,8 @@ _lib = None
 
 EXPORTED = ["ms2_create", "ms2_destroy", "ms2_forces", "ms2_ewald_kspace", "ms2_batch_create",
             "ms2_batch_destroy", "ms2_slot_footprint", "ms2_slot_admit", "ms2_slot_retire",
-            "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_last_error"]
+            "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_batch_timing",
+            "ms2_last_error"]
 
 
 def lib():
@@ -89,7 +93,8 @@ def lib():
         L.ms2_destroy.restype = None
         for fn in (L.ms2_forces, L.ms2_ewald_kspace):
             fn.argtypes = [vp, P(Params), c_int32, vp, vp, vp, vp, vp, vp, vp]
-        L.ms2_batch_create.argtypes = [vp, c_int32, c_size_t, P(vp)]
+        L.ms2_batch_create.argtypes = [vp, c_int32, c_size_t, c_int32, P(vp)]
+        L.ms2_batch_timing.argtypes = [vp, P(c_double), P(c_int32)]
         L.ms2_batch_destroy.argtypes = [vp]
         L.ms2_batch_destroy.restype = None
         L.ms2_slot_footprint.argtypes = [vp, P(System), P(c_size_t)]
@@ -232,10 +237,11 @@ def system_struct(system, precision: int, n_steps: Optional[int] = None):
 class Batch:
     """ms2_batch: device-resident slots advanced together by ms2_step."""
 
-    def __init__(self, ctx: Context, max_slots: int, hbm_budget: int = 0):
+    def __init__(self, ctx: Context, max_slots: int, hbm_budget: int = 0, plain_tiles: bool = False):
         self.ctx = ctx
         h = c_void_p()
-        check(lib().ms2_batch_create(ctx.handle, max_slots, hbm_budget, ctypes.byref(h)))
+        check(lib().ms2_batch_create(ctx.handle, max_slots, hbm_budget,
+                                     BATCH_PLAIN_TILES if plain_tiles else 0, ctypes.byref(h)))
         self.handle = h
         self.shapes = {}
 
@@ -268,8 +274,16 @@ class Batch:
         check(lib().ms2_slot_retire(self.handle, slot))
         self.shapes.pop(slot, None)
 
-    def step(self, n_steps: int, graph: bool = True, stream=None):
-        check(lib().ms2_step(self.handle, n_steps, STEP_GRAPH if graph else 0, _stream_ptr(stream)))
+    def step(self, n_steps: int, graph: bool = True, timing: bool = False, prepare: bool = False,
+             stream=None):
+        flags = (STEP_GRAPH if graph else 0) | (STEP_TIMING if timing else 0) | (STEP_PREPARE if prepare else 0)
+        check(lib().ms2_step(self.handle, n_steps, flags, _stream_ptr(stream)))
+
+    def pair_time_ms(self):
+        """(summed pair-kernel milliseconds, steps) of the last timed step call."""
+        ms, k = c_double(), c_int32()
+        check(lib().ms2_batch_timing(self.handle, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
 
     def status(self, slot: int, stream=None):
         steps, st = c_int64(), c_int32()
@@ -303,7 +317,8 @@ class Batch:
             buf("torque", (3, n))
         check(lib().ms2_sample(self.handle, slot, ctypes.byref(out), _stream_ptr(stream)))
         res = {"steps_done": out.steps_done, "status": out.status, "sums": np.array(out.sums[:]),
-               "ekin_trans": out.ekin_trans, "ekin_rot": out.ekin_rot, "moments": np.array(out.moments[:])}
+               "ekin_trans": out.ekin_trans, "ekin_rot": out.ekin_rot, "moments": np.array(out.moments[:]),
+               "pairs_total": out.pairs_total, "site_pairs_total": out.site_pairs_total}
         for k, v in arrays.items():
             res[k] = v.T.copy() if k in ("com", "quat", "vel", "omega", "force", "torque") else v
         return res
