@@ -154,15 +154,20 @@ static ms2_status build_species_table(const ms2_species* in, int nsp, SpeciesTab
 
 static int pick_class(const SpeciesTable& t) {
   int lj = 0, ch = 0, dp = 0, qd = 0;
+  bool central = true;
+  auto at_centre = [](const double* p) { return p[0] == 0.0 && p[1] == 0.0 && p[2] == 0.0; };
   for (int s = 0; s < t.nsp; ++s) {
-    lj = std::max(lj, t.sp[s].nlj);
-    ch = std::max(ch, t.sp[s].nch);
-    dp = std::max(dp, t.sp[s].ndp);
-    qd = std::max(qd, t.sp[s].nqd);
+    const SpeciesDev& d = t.sp[s];
+    lj = std::max(lj, d.nlj);
+    ch = std::max(ch, d.nch);
+    dp = std::max(dp, d.ndp);
+    qd = std::max(qd, d.nqd);
+    for (int a = 0; a < d.ndp; ++a) central &= at_centre(d.dp_pos[a]);
+    for (int a = 0; a < d.nqd; ++a) central &= at_centre(d.qd_pos[a]);
   }
   for (int c = 0; c < kNumClasses; ++c)
     if (lj <= kClassShapes[c].lj && ch <= kClassShapes[c].ch && dp <= kClassShapes[c].dp &&
-        qd <= kClassShapes[c].qd)
+        qd <= kClassShapes[c].qd && (central || !kClassShapes[c].central || (dp + qd) == 0))
       return c;
   return -1;
 }

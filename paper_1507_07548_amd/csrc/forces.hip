@@ -204,14 +204,23 @@ struct PairAcc {
 
 // One multipole site pair.  pa/ea: site a of i (offset, axis); pb/eb: site b
 // of j.  Adds the force on a to fs, -du/dea to gs (when a is oriented).
-template <typename Real, int TA, int TB>
+// CENTRAL: both sites at their molecules' centres, so r = R and the
+// volume-derivative terms follow from homogeneity (u ~ r^-p).
+template <typename Real, int TA, int TB, bool CENTRAL_CLASS>
 __device__ __forceinline__ void mp_site_pair(Real K, const Real* pa, const Real* ea, const Real* pb,
                                              const Real* eb, Real Rx, Real Ry, Real Rz, Real R2,
                                              PairAcc<Real>& acc, Real* fs, Real* gs, bool rf_dd,
                                              Real krf) {
   constexpr int p = MpPower<TA, TB>::p;
-  const Real rx = Rx + pa[0] - pb[0], ry = Ry + pa[1] - pb[1], rz = Rz + pa[2] - pb[2];
-  const Real r2 = rx * rx + ry * ry + rz * rz;
+  // the class guarantees centred dipoles/quadrupoles, not centred charges
+  constexpr bool CENTRAL = CENTRAL_CLASS && TA != 1 && TB != 1;
+  Real rx = Rx, ry = Ry, rz = Rz, r2 = R2;
+  if constexpr (!CENTRAL) {
+    rx += pa[0] - pb[0];
+    ry += pa[1] - pb[1];
+    rz += pa[2] - pb[2];
+    r2 = rx * rx + ry * ry + rz * rz;
+  }
   const Real ir = rsq_(r2), ir2 = ir * ir;
   const Real nx = rx * ir, ny = ry * ir, nz = rz * ir;
   Real ca = 0, cb = 0, cab = 0;
@@ -220,17 +229,17 @@ __device__ __forceinline__ void mp_site_pair(Real K, const Real* pa, const Real*
   if constexpr (TA != 1 && TB != 1) cab = ea[0] * eb[0] + ea[1] * eb[1] + ea[2] * eb[2];
   const Poly<Real> q = mp_poly<Real, TA, TB>(ca, cb, cab);
   const Real Kp = K * ipow<Real, p>(ir);
-  acc.uel += Kp * q.P;
-  // force on a: -grad_r u, grad_r ca = (ea - ca n)/r
+  const Real u = Kp * q.P;
+  acc.uel += u;
+  // force on a = -grad_r u = (K r^-p / r) [(p P + Pa ca + Pb cb) n - Pa ea - Pb eb]
   const Real A = Kp * ir;
-  Real hx = -Real(p) * q.P * nx, hy = -Real(p) * q.P * ny, hz = -Real(p) * q.P * nz;
-  if constexpr (TA != 1) {
-    hx += q.Pa * (ea[0] - ca * nx); hy += q.Pa * (ea[1] - ca * ny); hz += q.Pa * (ea[2] - ca * nz);
-  }
-  if constexpr (TB != 1) {
-    hx += q.Pb * (eb[0] - cb * nx); hy += q.Pb * (eb[1] - cb * ny); hz += q.Pb * (eb[2] - cb * nz);
-  }
-  const Real fx = -A * hx, fy = -A * hy, fz = -A * hz;
+  Real sdot = Real(p) * q.P;
+  if constexpr (TA != 1) sdot += q.Pa * ca;
+  if constexpr (TB != 1) sdot += q.Pb * cb;
+  Real fx = sdot * nx, fy = sdot * ny, fz = sdot * nz;
+  if constexpr (TA != 1) { fx -= q.Pa * ea[0]; fy -= q.Pa * ea[1]; fz -= q.Pa * ea[2]; }
+  if constexpr (TB != 1) { fx -= q.Pb * eb[0]; fy -= q.Pb * eb[1]; fz -= q.Pb * eb[2]; }
+  fx *= A; fy *= A; fz *= A;
   fs[0] += fx; fs[1] += fy; fs[2] += fz;
   acc.fx += fx; acc.fy += fy; acc.fz += fz;
   if constexpr (TA != 1) {
@@ -238,29 +247,33 @@ __device__ __forceinline__ void mp_site_pair(Real K, const Real* pa, const Real*
     if constexpr (TB != 1) { gx += q.Pc * eb[0]; gy += q.Pc * eb[1]; gz += q.Pc * eb[2]; }
     gs[0] -= Kp * gx; gs[1] -= Kp * gy; gs[2] -= Kp * gz;
   }
-  // second derivative of u(r + t R) at t = 0
-  const Real beta = nx * Rx + ny * Ry + nz * Rz;
-  const Real w = R2 - beta * beta;
-  Real F1 = 0, F2 = 0;
-  Real ca1 = 0, cb1 = 0;
-  if constexpr (TA != 1) {
-    ca1 = ((ea[0] * Rx + ea[1] * Ry + ea[2] * Rz) - ca * beta) * ir;
-    const Real ca2 = -(Real(2) * ca1 * beta + ca * w * ir) * ir;
-    F1 += q.Pa * ca1;
-    F2 += q.Paa * ca1 * ca1 + q.Pa * ca2;
+  if constexpr (CENTRAL) {
+    acc.uss += Real(p * (p + 1)) * u;
+  } else {
+    // second derivative of u(r + t R) at t = 0
+    const Real beta = nx * Rx + ny * Ry + nz * Rz;
+    const Real w = R2 - beta * beta;
+    Real F1 = 0, F2 = 0;
+    Real ca1 = 0, cb1 = 0;
+    if constexpr (TA != 1) {
+      ca1 = ((ea[0] * Rx + ea[1] * Ry + ea[2] * Rz) - ca * beta) * ir;
+      const Real ca2 = -(Real(2) * ca1 * beta + ca * w * ir) * ir;
+      F1 += q.Pa * ca1;
+      F2 += q.Paa * ca1 * ca1 + q.Pa * ca2;
+    }
+    if constexpr (TB != 1) {
+      cb1 = ((eb[0] * Rx + eb[1] * Ry + eb[2] * Rz) - cb * beta) * ir;
+      const Real cb2 = -(Real(2) * cb1 * beta + cb * w * ir) * ir;
+      F1 += q.Pb * cb1;
+      F2 += q.Pbb * cb1 * cb1 + q.Pb * cb2;
+    }
+    if constexpr (TA != 1 && TB != 1) F2 += Real(2) * q.Pab * ca1 * cb1;
+    const Real f1 = -Real(p) * ir * beta;
+    const Real f2 = ir2 * (Real(p * (p + 1)) * beta * beta - Real(p) * w);
+    acc.uss += Kp * (F2 + Real(2) * F1 * f1 + q.P * f2);
   }
-  if constexpr (TB != 1) {
-    cb1 = ((eb[0] * Rx + eb[1] * Ry + eb[2] * Rz) - cb * beta) * ir;
-    const Real cb2 = -(Real(2) * cb1 * beta + cb * w * ir) * ir;
-    F1 += q.Pb * cb1;
-    F2 += q.Pbb * cb1 * cb1 + q.Pb * cb2;
-  }
-  if constexpr (TA != 1 && TB != 1) F2 += Real(2) * q.Pab * ca1 * cb1;
-  const Real f1 = -Real(p) * ir * beta;
-  const Real f2 = ir2 * (Real(p * (p + 1)) * beta * beta - Real(p) * w);
-  acc.uss += Kp * (F2 + Real(2) * F1 * f1 + q.P * f2);
   if constexpr (TA == 2 && TB == 2) {
-    if (rf_dd) {  // Barker-Watts reaction field: -2 kRF K (ea.eb); no force
+    if (rf_dd) {  // Barker-Watts reaction field: -2 kRF K (ea.eb); no force, no volume terms
       acc.uel -= Real(2) * krf * K * cab;
       gs[0] += Real(2) * krf * K * eb[0];
       gs[1] += Real(2) * krf * K * eb[1];
@@ -286,6 +299,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
   constexpr int NDP = S.dp > 0 ? S.dp : 1;
   constexpr int NQD = S.qd > 0 ? S.qd : 1;
   constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
+  constexpr bool CENTRAL = S.central != 0;
 
   __shared__ double s_com[3][TJ];
   __shared__ int s_sp[TJ];
@@ -376,6 +390,8 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
     __syncthreads();
 
     // phase 1: cut-off bits, one 64-bit word per 64 j molecules
+    const int nvalid = min(TJ, min(it.j1, n) - jt);   // uniform over the block
+    const int iself = i - jt;                          // lane's own molecule in this tile, if any
     unsigned long long mask[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -384,7 +400,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
         const int jj = w * 64 + b;
         double dx, dy, dz, r2;
         min_image(xi, yi, zi, s_com[0][jj], s_com[1][jj], s_com[2][jj], L, invL, dx, dy, dz, r2);
-        const bool ok = (r2 < rc2) && (s_sp[jj] >= 0) && (jt + jj != i);
+        const unsigned ok = (unsigned)(r2 < rc2) & (unsigned)(jj < nvalid) & (unsigned)(jj != iself);
         m |= (unsigned long long)ok << b;
       }
       mask[w] = iv ? m : 0ull;
@@ -495,7 +511,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
                 const Real pb[3] = {s_site[OFF_DP + 6 * b][jj], s_site[OFF_DP + 6 * b + 1][jj], s_site[OFF_DP + 6 * b + 2][jj]};
                 const Real eb[3] = {s_site[OFF_DP + 6 * b + 3][jj], s_site[OFF_DP + 6 * b + 4][jj], s_site[OFF_DP + 6 * b + 5][jj]};
                 Real gdummy[3] = {0, 0, 0};
-                mp_site_pair<Real, 1, 2>(s_mch[spi][a] * s_mdp[spj][b] * kk, pa, zero3, pb, eb, Rx, Ry, Rz, R2, acc, fc[a], gdummy, false, krf);
+                mp_site_pair<Real, 1, 2, CENTRAL>(s_mch[spi][a] * s_mdp[spj][b] * kk, pa, zero3, pb, eb, Rx, Ry, Rz, R2, acc, fc[a], gdummy, false, krf);
               }
             }
             if constexpr (S.qd > 0) {
@@ -505,7 +521,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
                 const Real pb[3] = {s_site[OFF_QD + 6 * b][jj], s_site[OFF_QD + 6 * b + 1][jj], s_site[OFF_QD + 6 * b + 2][jj]};
                 const Real eb[3] = {s_site[OFF_QD + 6 * b + 3][jj], s_site[OFF_QD + 6 * b + 4][jj], s_site[OFF_QD + 6 * b + 5][jj]};
                 Real gdummy[3] = {0, 0, 0};
-                mp_site_pair<Real, 1, 3>(s_mch[spi][a] * s_mqd[spj][b] * kk, pa, zero3, pb, eb, Rx, Ry, Rz, R2, acc, fc[a], gdummy, false, krf);
+                mp_site_pair<Real, 1, 3, CENTRAL>(s_mch[spi][a] * s_mqd[spj][b] * kk, pa, zero3, pb, eb, Rx, Ry, Rz, R2, acc, fc[a], gdummy, false, krf);
               }
             }
           }
@@ -522,7 +538,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
               for (int b = 0; b < S.ch; ++b) {
                 if (b >= nch_j) break;
                 const Real pb[3] = {s_site[OFF_CH + 3 * b][jj], s_site[OFF_CH + 3 * b + 1][jj], s_site[OFF_CH + 3 * b + 2][jj]};
-                mp_site_pair<Real, 2, 1>(s_mdp[spi][a] * s_mch[spj][b] * kk, pa, ea, pb, zero3, Rx, Ry, Rz, R2, acc, fd[a], gd[a], false, krf);
+                mp_site_pair<Real, 2, 1, CENTRAL>(s_mdp[spi][a] * s_mch[spj][b] * kk, pa, ea, pb, zero3, Rx, Ry, Rz, R2, acc, fd[a], gd[a], false, krf);
               }
             }
 #pragma unroll
@@ -530,7 +546,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
               if (b >= ndp_j) break;
               const Real pb[3] = {s_site[OFF_DP + 6 * b][jj], s_site[OFF_DP + 6 * b + 1][jj], s_site[OFF_DP + 6 * b + 2][jj]};
               const Real eb[3] = {s_site[OFF_DP + 6 * b + 3][jj], s_site[OFF_DP + 6 * b + 4][jj], s_site[OFF_DP + 6 * b + 5][jj]};
-              mp_site_pair<Real, 2, 2>(s_mdp[spi][a] * s_mdp[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fd[a], gd[a], rf_dd, krf);
+              mp_site_pair<Real, 2, 2, CENTRAL>(s_mdp[spi][a] * s_mdp[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fd[a], gd[a], rf_dd, krf);
             }
             if constexpr (S.qd > 0) {
 #pragma unroll
@@ -538,7 +554,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
                 if (b >= nqd_j) break;
                 const Real pb[3] = {s_site[OFF_QD + 6 * b][jj], s_site[OFF_QD + 6 * b + 1][jj], s_site[OFF_QD + 6 * b + 2][jj]};
                 const Real eb[3] = {s_site[OFF_QD + 6 * b + 3][jj], s_site[OFF_QD + 6 * b + 4][jj], s_site[OFF_QD + 6 * b + 5][jj]};
-                mp_site_pair<Real, 2, 3>(s_mdp[spi][a] * s_mqd[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fd[a], gd[a], false, krf);
+                mp_site_pair<Real, 2, 3, CENTRAL>(s_mdp[spi][a] * s_mqd[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fd[a], gd[a], false, krf);
               }
             }
           }
@@ -555,7 +571,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
               for (int b = 0; b < S.ch; ++b) {
                 if (b >= nch_j) break;
                 const Real pb[3] = {s_site[OFF_CH + 3 * b][jj], s_site[OFF_CH + 3 * b + 1][jj], s_site[OFF_CH + 3 * b + 2][jj]};
-                mp_site_pair<Real, 3, 1>(s_mqd[spi][a] * s_mch[spj][b] * kk, pa, ea, pb, zero3, Rx, Ry, Rz, R2, acc, fq[a], gq[a], false, krf);
+                mp_site_pair<Real, 3, 1, CENTRAL>(s_mqd[spi][a] * s_mch[spj][b] * kk, pa, ea, pb, zero3, Rx, Ry, Rz, R2, acc, fq[a], gq[a], false, krf);
               }
             }
             if constexpr (S.dp > 0) {
@@ -564,7 +580,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
                 if (b >= ndp_j) break;
                 const Real pb[3] = {s_site[OFF_DP + 6 * b][jj], s_site[OFF_DP + 6 * b + 1][jj], s_site[OFF_DP + 6 * b + 2][jj]};
                 const Real eb[3] = {s_site[OFF_DP + 6 * b + 3][jj], s_site[OFF_DP + 6 * b + 4][jj], s_site[OFF_DP + 6 * b + 5][jj]};
-                mp_site_pair<Real, 3, 2>(s_mqd[spi][a] * s_mdp[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fq[a], gq[a], false, krf);
+                mp_site_pair<Real, 3, 2, CENTRAL>(s_mqd[spi][a] * s_mdp[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fq[a], gq[a], false, krf);
               }
             }
 #pragma unroll
@@ -572,7 +588,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
               if (b >= nqd_j) break;
               const Real pb[3] = {s_site[OFF_QD + 6 * b][jj], s_site[OFF_QD + 6 * b + 1][jj], s_site[OFF_QD + 6 * b + 2][jj]};
               const Real eb[3] = {s_site[OFF_QD + 6 * b + 3][jj], s_site[OFF_QD + 6 * b + 4][jj], s_site[OFF_QD + 6 * b + 5][jj]};
-              mp_site_pair<Real, 3, 3>(s_mqd[spi][a] * s_mqd[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fq[a], gq[a], false, krf);
+              mp_site_pair<Real, 3, 3, CENTRAL>(s_mqd[spi][a] * s_mqd[spj][b] * kk, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fq[a], gq[a], false, krf);
             }
           }
         }

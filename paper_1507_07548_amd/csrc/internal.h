@@ -21,17 +21,20 @@ constexpr int kMolTile = 64;      // molecules per structure-factor block
 constexpr int kMaxRdfTypes = 16;
 
 // Model classes: compile-time upper bounds on the sites of each type per
-// molecule.  Each class is one instantiation of the pair kernel; a system
-// runs in the smallest class that covers every species it uses.
-struct ClassShape { int lj, ch, dp, qd; };
+// molecule, and whether every dipole/quadrupole sits at the centre of mass
+// (then a multipole pair depends on R only through its direction and
+// magnitude: r = R, and U_s = -p u, U_ss = p (p+1) u for u ~ r^-p).  Each
+// class is one instantiation of the pair kernel; a context runs in the first
+// class that covers all of its species.
+struct ClassShape { int lj, ch, dp, qd, central; };
 constexpr int kNumClasses = 6;
 constexpr ClassShape kClassShapes[kNumClasses] = {
-    {1, 0, 0, 0},   // one-centre LJ
-    {2, 0, 0, 1},   // two-centre LJ + linear quadrupole
-    {1, 3, 0, 0},   // LJ + up to three charges (water-like, ions)
-    {1, 0, 1, 0},   // Stockmayer
-    {2, 2, 1, 1},   // small mixed
-    {4, 4, 2, 2},   // general
+    {1, 0, 0, 0, 1},   // one-centre LJ
+    {2, 0, 0, 1, 1},   // two-centre LJ + linear quadrupole at the centre
+    {1, 3, 0, 0, 1},   // LJ + up to three charges (water-like, ions)
+    {1, 0, 1, 0, 1},   // Stockmayer (dipole at the centre)
+    {2, 2, 1, 1, 0},   // small mixed, multipoles anywhere
+    {4, 4, 2, 2, 0},   // general
 };
 __host__ __device__ constexpr int class_reals(int c) {
   return 3 * (kClassShapes[c].lj + kClassShapes[c].ch) + 6 * (kClassShapes[c].dp + kClassShapes[c].qd);
