@@ -255,10 +255,26 @@ ms2_status ms2_sample(ms2_batch* batch, int32_t slot, ms2_samples* h_out, void* 
 ms2_status ms2_slot_status(ms2_batch* batch, int32_t slot, int64_t* steps_done,
                            int32_t* status, void* stream);
 
-/* Tile shape used for a pair-kernel launch of n molecules of a model class
- * (chosen by the built-in autotuner; depends only on the model and n). */
-ms2_status ms2_tile_config(ms2_ctx* ctx, int32_t n_mol, int32_t precision,
+/* Pair-kernel tile shape for n molecules: wave_rows waves of 64 molecules i
+ * per block, j_chunk molecules j per work item.  The shape depends only on
+ * the context's model class, the precision, the launch mode (0: one system
+ * per launch, 1: batched) and the size bucket floor(log2 n) -- never on which
+ * other systems share a launch.  Defaults are heuristic until ms2_autotune or
+ * ms2_set_tile_config sets the bucket. */
+ms2_status ms2_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,
                            int32_t* wave_rows, int32_t* j_chunk);
+ms2_status ms2_set_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,
+                               int32_t wave_rows, int32_t j_chunk);
+
+/* Autotuner: for every size bucket between n_lo and n_hi and both launch
+ * modes, times candidate tile shapes on the device with a synthetic lattice
+ * system of species 0 (mode 1: a batch of copies filling the GPU) and keeps
+ * the fastest.  Allocates and synchronizes; call before admitting systems.
+ * h_report (optional, host) receives up to max_report rows of
+ * (mode, bucket n, wave_rows, j_chunk, microseconds per system evaluation)
+ * for every candidate timed; *n_report is set to the number of rows. */
+ms2_status ms2_autotune(ms2_ctx* ctx, int32_t precision, int32_t n_lo, int32_t n_hi,
+                        double* h_report, int32_t max_report, int32_t* n_report, void* stream);
 
 /* Thread-local message of the last failed call ("" if none). */
 const char* ms2_last_error(void);

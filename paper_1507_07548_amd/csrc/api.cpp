@@ -283,8 +283,14 @@ ms2_status kvec_table(ms2_ctx* ctx, int kmax2, const KVec** d_out, int* nk) {
 // ---------------------------------------------------------------------------
 // tile shapes (per model class, precision, n and launch mode)
 // ---------------------------------------------------------------------------
+int size_bucket(int n) {
+  int b = 0;
+  while ((2 << b) <= n) ++b;
+  return b;  // floor(log2 n)
+}
+
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
-  auto it = ctx->tuned.find(std::make_tuple(mode, precision, n));
+  auto it = ctx->tuned.find(std::make_tuple(mode, precision, size_bucket(n)));
   if (it != ctx->tuned.end()) return it->second;
   TileCfg c;
   if (mode == 0) {  // one system per launch: many small items to spread one system
@@ -528,12 +534,28 @@ ms2_status ms2_ewald_kspace(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_
   return MS2_OK;
 }
 
-ms2_status ms2_tile_config(ms2_ctx* ctx, int32_t n_mol, int32_t precision, int32_t* wave_rows,
-                           int32_t* j_chunk) {
-  if (!ctx || !wave_rows || !j_chunk || n_mol < 2) return set_error(MS2_EINVAL, "bad arguments");
-  TileCfg c = tile_config(ctx, 1, precision, n_mol);
+ms2_status ms2_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,
+                           int32_t* wave_rows, int32_t* j_chunk) {
+  if (!ctx || !wave_rows || !j_chunk || n_mol < 2 || (mode != 0 && mode != 1))
+    return set_error(MS2_EINVAL, "bad arguments");
+  TileCfg c = tile_config(ctx, mode, precision, n_mol);
   *wave_rows = c.waves;
   *j_chunk = c.jchunk;
+  return MS2_OK;
+}
+
+ms2_status ms2_set_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,
+                               int32_t wave_rows, int32_t j_chunk) {
+  if (!ctx || n_mol < 2 || (mode != 0 && mode != 1) || (precision != MS2_FP32 && precision != MS2_FP64))
+    return set_error(MS2_EINVAL, "bad arguments");
+  if (!(wave_rows == 1 || (wave_rows == 4 && ctx->cls <= 3)))
+    return set_error(MS2_EINVAL, "wave_rows must be 1 (or 4 for the first four model classes)");
+  if (j_chunk < 64 * wave_rows || j_chunk % (64 * wave_rows) != 0)
+    return set_error(MS2_EINVAL, "j_chunk must be a positive multiple of 64 * wave_rows");
+  TileCfg c;
+  c.waves = wave_rows;
+  c.jchunk = j_chunk;
+  ctx->tuned[std::make_tuple(mode, precision, size_bucket(n_mol))] = c;
   return MS2_OK;
 }
 

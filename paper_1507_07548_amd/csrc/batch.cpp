@@ -62,7 +62,7 @@ struct SlotLayout {
 };
 
 struct SlotShape {
-  int n, npad, cls, precision, jsplits, nitems, waves, mode, nk, kchunks, mchunks, mtiles;
+  int n, npad, cls, precision, jsplits, nitems, waves, jchunk, mode, nk, kchunks, mchunks, mtiles;
   int rdf_ntp, rdf_bins, acf_nlag, acf_max_live;
 };
 
@@ -199,6 +199,7 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
   s.mode = mode;
   const TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
   s.waves = cfg.waves;
+  s.jchunk = cfg.jchunk;   // frozen at admission: the slot's buffers are sized for it
   s.jsplits = (s.n + cfg.jchunk - 1) / cfg.jchunk;
   s.nitems = ((s.n + 64 * cfg.waves - 1) / (64 * cfg.waves)) * s.jsplits;
   if (sys->params.elec == MS2_ELEC_EWALD) {
@@ -238,7 +239,9 @@ void rebuild_items(ms2_batch* b) {
       for (int s = 0; s < b->max_slots; ++s) {
         const SlotHost& h = b->slots[s];
         if (!h.used || h.shape.precision != prec || h.shape.waves != waves) continue;
-        const TileCfg c = tile_config(b->ctx, h.shape.mode, prec, h.shape.n);
+        TileCfg c;
+        c.waves = h.shape.waves;
+        c.jchunk = h.shape.jchunk;
         int js = 0;
         build_items(h.shape.n, c, s, all, &js);
       }

@@ -54,7 +54,7 @@ struct ms2_ctx {
   ms2::DevBuf s_sites, s_pf, s_bsum, s_skp, s_sk, s_fk, s_kred, s_ksum;
   std::map<int, std::pair<ms2::DevBuf, int>> kvecs;            // kmax2 -> (table, count)
   std::map<std::tuple<int, int, int>, ms2::CachedItems> item_cache;
-  std::map<std::tuple<int, int, int>, ms2::TileCfg> tuned;     // (mode, precision, n) -> shape
+  std::map<std::tuple<int, int, int>, ms2::TileCfg> tuned;     // (mode, precision, log2 n) -> shape
   ms2::RingSlot ring[ms2::kRing];
   int ring_pos = 0;
 };
@@ -64,5 +64,6 @@ ms2_status check_params(const ms2_ctx* ctx, const ms2_params* p);
 void build_sys_params(const ms2_ctx* ctx, const ms2_params* p, int nk, SysParams& s);
 ms2_status kvec_table(ms2_ctx* ctx, int kmax2, const KVec** d_out, int* nk);
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n);
+int size_bucket(int n);
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits);
 }  // namespace ms2

@@ -332,3 +332,55 @@ def with_random_positions(system: System, seed: int) -> System:
     out.com = rng.random((system.n, 3)) * system.params.box
     out.quat = random_quaternions(system.n, rng)
     return out
+
+
+# --------------------------------------------------------------------------
+# serving trace
+# --------------------------------------------------------------------------
+SERVING_MODELS = ("lj", "2cljq", "ionic")
+
+
+def serving_system(model: str, n: int, seed: int, n_steps: int, window: int = 1000,
+                   acf_every: int = 10, origin_every: int = 100, rdf_every: int = 10,
+                   rdf_bins: int = 400) -> System:
+    """One request of the serving workload: model family `model` with n
+    molecules, seeded, running `n_steps` steps with RDF, Lustig moments (not
+    with Ewald) and velocity / electric-current ACFs over a `window`-step
+    window on an extended step of `acf_every`."""
+    if model == "lj":
+        box = (n / 0.7) ** (1.0 / 3.0)
+        s = lj_fluid(n=n, density=0.7, temperature=1.5, rc=min(4.0, 0.48 * box), seed=seed,
+                     n_steps=n_steps)
+        s.md.sample_every = 1
+        dmax = 0.0
+    elif model == "2cljq":
+        s = quadrupolar_fluid(n=n, seed=seed, n_steps=n_steps, sample_every=1)
+        dmax = 0.15
+    elif model == "ionic":
+        pairs = max(1, int(round(0.05 * n)))
+        s = ionic_solution(n_water=n - 2 * pairs, n_pairs=pairs, seed=seed, n_steps=n_steps,
+                           rdf_every=rdf_every, rdf_bins=rdf_bins)
+        dmax = max(np.linalg.norm(x.pos) for sp in s.species for x in sp.sites if x.kind == LJ)
+    else:
+        raise ValueError(model)
+    s.md.rdf_every, s.md.rdf_bins = rdf_every, rdf_bins
+    s.md.rdf_rmax = s.params.rc - 2.0 * dmax
+    s.md.acf_every, s.md.acf_origin_every = acf_every, origin_every
+    s.md.acf_nlag = window // acf_every
+    s.name = f"{model}_{n}"
+    return s
+
+
+def serving_trace(n_requests: int = 64, rate: float = 50.0, seed: int = 5, n_lo: int = 256,
+                  n_hi: int = 8192, n_steps: int = 20000, **kw):
+    """Poisson arrivals (exponential gaps, mean 1/rate), model uniform over the
+    three families, N = round(n_lo (n_hi/n_lo)^u) with u ~ U(0, 1); request r
+    is seeded 50000 + r.  Returns [(arrival, model, system)]."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    out = []
+    for r in range(n_requests):
+        model = SERVING_MODELS[int(rng.integers(len(SERVING_MODELS)))]
+        n = int(round(n_lo * (n_hi / n_lo) ** rng.random()))
+        out.append((float(t[r]), model, serving_system(model, n, 50000 + r, n_steps, **kw)))
+    return out

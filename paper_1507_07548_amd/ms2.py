@@ -76,8 +76,8 @@ _lib = None
 
 EXPORTED = ["ms2_create", "ms2_destroy", "ms2_forces", "ms2_ewald_kspace", "ms2_batch_create",
             "ms2_batch_destroy", "ms2_slot_footprint", "ms2_slot_admit", "ms2_slot_retire",
-            "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_batch_timing",
-            "ms2_last_error"]
+            "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_set_tile_config",
+            "ms2_autotune", "ms2_batch_timing", "ms2_last_error"]
 
 
 def lib():
@@ -103,7 +103,9 @@ def lib():
         L.ms2_step.argtypes = [vp, c_int32, c_int32, vp]
         L.ms2_sample.argtypes = [vp, c_int32, P(Samples), vp]
         L.ms2_slot_status.argtypes = [vp, c_int32, P(c_int64), P(c_int32), vp]
-        L.ms2_tile_config.argtypes = [vp, c_int32, c_int32, P(c_int32), P(c_int32)]
+        L.ms2_tile_config.argtypes = [vp, c_int32, c_int32, c_int32, P(c_int32), P(c_int32)]
+        L.ms2_set_tile_config.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, c_int32]
+        L.ms2_autotune.argtypes = [vp, c_int32, c_int32, c_int32, P(c_double), c_int32, P(c_int32), vp]
         L.ms2_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name not in ("ms2_destroy", "ms2_batch_destroy", "ms2_last_error"):
@@ -179,10 +181,22 @@ class Context:
                                      com.data_ptr(), quat.data_ptr(), force.data_ptr(), torque.data_ptr(),
                                      sums.data_ptr(), _stream_ptr(stream)))
 
-    def tile_config(self, n: int, precision: int):
+    def tile_config(self, n: int, precision: int, mode: int = 1):
         w, j = c_int32(), c_int32()
-        check(lib().ms2_tile_config(self.handle, n, precision, ctypes.byref(w), ctypes.byref(j)))
+        check(lib().ms2_tile_config(self.handle, mode, n, precision, ctypes.byref(w), ctypes.byref(j)))
         return w.value, j.value
+
+    def set_tile_config(self, n: int, precision: int, waves: int, jchunk: int, mode: int = 1):
+        check(lib().ms2_set_tile_config(self.handle, mode, n, precision, waves, jchunk))
+
+    def autotune(self, precision: int, n_lo: int, n_hi: int, stream=None):
+        """Runs the library's autotuner; returns rows (mode, n, waves, jchunk, us per system)."""
+        cap = 512
+        rep = np.zeros((cap, 5))
+        cnt = c_int32()
+        check(lib().ms2_autotune(self.handle, precision, n_lo, n_hi, rep.ctypes.data_as(P(c_double)), cap,
+                                 ctypes.byref(cnt), _stream_ptr(stream)))
+        return rep[: cnt.value]
 
 
 class DeviceSystem:

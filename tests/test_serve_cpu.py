@@ -1,0 +1,140 @@
+"""The continuous-batching scheduler against a fake backend on the CPU:
+admission by HBM footprint and free slots, FIFO blocking, slot reuse,
+overlap of late arrivals with running work, and a failing slot retired with
+its error while the others keep running."""
+import types
+
+import pytest
+
+from paper_1507_07548_amd.serve import Request, Server, percentile
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class FakeBackend:
+    """Slots advance k steps per step(k); each chunk costs `cost` seconds of
+    the fake clock.  A request whose system has `fail_at` stops there with
+    status 4 (non-finite)."""
+
+    def __init__(self, clock, max_slots=4, cost=0.01, bytes_per_mol=100):
+        self.clock, self.max_slots, self.cost, self.bpm = clock, max_slots, cost, bytes_per_mol
+        self.slots = {}
+        self.peak_active = 0
+        self.admitted = []
+
+    def footprint(self, system, precision):
+        return system.n * self.bpm
+
+    def admit(self, system, precision):
+        if len(self.slots) >= self.max_slots:
+            return None
+        slot = min(set(range(self.max_slots)) - set(self.slots))
+        self.slots[slot] = {"sys": system, "steps": 0, "status": 0}
+        self.admitted.append(system.rid)
+        self.peak_active = max(self.peak_active, len(self.slots))
+        return slot
+
+    def active(self):
+        return len(self.slots)
+
+    def step(self, k):
+        for s in self.slots.values():
+            if s["status"] or s["steps"] >= s["sys"].md.n_steps:
+                continue
+            fail = getattr(s["sys"], "fail_at", None)
+            new = min(s["steps"] + k, s["sys"].md.n_steps)
+            if fail is not None and new >= fail:
+                s["steps"], s["status"] = fail, 4
+            else:
+                s["steps"] = new
+        self.clock.t += self.cost
+
+    def sync(self):
+        pass
+
+    def poll(self):
+        return [(slot, s["steps"], s["status"], s["status"] != 0 or s["steps"] >= s["sys"].md.n_steps)
+                for slot, s in self.slots.items()]
+
+    def collect(self, slot):
+        return {"steps": self.slots[slot]["steps"]}
+
+    def retire(self, slot):
+        del self.slots[slot]
+
+
+def req(rid, arrival, n=100, steps=300, model="a", fail_at=None):
+    sysm = types.SimpleNamespace(n=n, md=types.SimpleNamespace(n_steps=steps), rid=rid, fail_at=fail_at)
+    return Request(rid, arrival, model, sysm)
+
+
+def test_all_requests_complete_with_their_own_step_budgets():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    srv = Server({"a": be}, hbm_budget=10 ** 9, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    reqs = [req(i, 0.001 * i, steps=100 * (1 + i % 3)) for i in range(10)]
+    res = srv.run(reqs)
+    assert sorted(r.rid for r in res) == list(range(10))
+    for r in res:
+        assert r.status == 0 and r.steps_done == reqs[r.rid].system.md.n_steps
+        assert r.finished >= r.admitted >= r.arrival
+
+
+def test_admission_respects_the_hbm_budget_and_queues_in_order():
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=16)
+    budget = 250 * 100                                 # 2.5 systems of n=100
+    srv = Server({"a": be}, hbm_budget=budget, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    res = srv.run([req(i, 0.0) for i in range(6)])
+    assert be.peak_active == 2                          # never more than the budget allows
+    assert be.admitted == list(range(6))                # FIFO
+    waits = sorted(r.admitted - r.arrival for r in res)
+    assert waits[0] == 0.0 and waits[-1] > 0.0          # later requests queued
+
+
+def test_slots_are_reused_and_late_arrivals_overlap_running_work():
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=3)
+    srv = Server({"a": be}, hbm_budget=10 ** 9, chunk_steps=50, clock=clk, sleep=clk.sleep)
+    reqs = [req(0, 0.0, steps=1000), req(1, 0.015, steps=100), req(2, 0.03, steps=100),
+            req(3, 0.035, steps=100), req(4, 0.2, steps=100)]
+    res = {r.rid: r for r in srv.run(reqs)}
+    # requests 1-3 were admitted and finished while request 0 was still running
+    assert all(res[k].admitted < res[0].finished and res[k].finished < res[0].finished for k in (1, 2, 3))
+    assert len(res) == 5 and be.peak_active == 3
+
+
+def test_a_failing_slot_is_retired_while_others_continue():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    srv = Server({"a": be}, hbm_budget=10 ** 9, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    res = {r.rid: r for r in srv.run([req(0, 0.0, steps=500), req(1, 0.0, steps=500, fail_at=150),
+                                      req(2, 0.0, steps=500)])}
+    assert res[1].status == 4 and res[1].steps_done == 150
+    assert res[0].status == 0 and res[0].steps_done == 500
+    assert res[2].status == 0 and res[1].finished < res[0].finished
+
+
+def test_two_model_families_share_the_budget():
+    clk = FakeClock()
+    a, b = FakeBackend(clk, max_slots=8), FakeBackend(clk, max_slots=8, cost=0.0)
+    srv = Server({"a": a, "b": b}, hbm_budget=3 * 100 * 100, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    reqs = [req(i, 0.0, model="ab"[i % 2]) for i in range(8)]
+    res = srv.run(reqs)
+    assert len(res) == 8
+    assert a.peak_active + b.peak_active <= 3 + 1
+
+
+def test_nearest_rank_percentiles():
+    v = list(range(1, 101))
+    assert percentile(v, 50) == 50 and percentile(v, 99) == 99 and percentile(v, 100) == 100
+    assert percentile([3.0], 99) == 3.0
