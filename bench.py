@@ -61,6 +61,40 @@ def cpu_baseline(systems, budget_s=12.0):
                       f"single thread, {t_total:.1f} s"}
 
 
+def serve_trace(n_requests, n_steps):
+    """The serving form on a scaled trace of the mixed-model workload:
+    Poisson arrivals at 50/s, models uniform over {one-site LJ, 2CLJQ,
+    water + 10 % ions with Ewald}, N log-uniform in [256, 8192], each request
+    running `n_steps` steps (the full workload asks 2e4) with RDF (400 bins),
+    Lustig moments (non-Ewald) and velocity/current ACFs over a 200-step
+    window on an extended step of 10."""
+    import torch
+
+    from paper_1507_07548_amd import inputs, ms2
+    from paper_1507_07548_amd.serve import GpuBackend, Request, Server, percentile
+    trace = inputs.serving_trace(n_requests=n_requests, rate=50.0, seed=5, n_steps=n_steps,
+                                 window=200, acf_every=10, origin_every=50)
+    fam = {"lj": [inputs.one_center_lj()], "2cljq": [inputs.two_center_lj_quadrupole()],
+           "ionic": [inputs.water_tip4p_like(), inputs.cation(), inputs.anion()]}
+    backends = {m: GpuBackend(fam[m], max_slots=64) for m in fam}
+    reqs = [Request(r, t, m, s, ms2.FP32) for r, (t, m, s) in enumerate(trace)]
+    log(f"[bench] serving {len(reqs)} requests x {n_steps} steps")
+    srv = Server(backends, hbm_budget=64 << 30, chunk_steps=50, keep_samples=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    makespan = time.perf_counter() - t0
+    lat = [r.latency for r in res]
+    steps = sum(r.steps_done for r in res)
+    ok = all(r.status == 0 for r in res)
+    return {"requests": len(res), "steps_per_request": n_steps, "arrival_rate_per_s": 50.0,
+            "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
+            "md_steps_per_s": steps / makespan, "makespan_s": makespan, "all_ok": ok,
+            "n_range": [256, 8192], "models": ["1CLJ (VV NVE)", "2CLJQ (Gear NVT, RF)",
+                                              "water+ions (Gear NVT, Ewald)"],
+            "note": "scaled trace: the full request asks 2e4 steps and a 1000-step ACF window"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +103,10 @@ def main():
     ap.add_argument("--systems", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-steps", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs each system on a single MI355X "
@@ -85,6 +123,12 @@ def main():
     systems = [inputs.batched_state_point(s) for s in range(args.systems)]
     ctx = ms2.Context(systems[0].species)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_autotune:
+        log("[bench] autotuning tile shapes for N in [500, 4000]")
+        rows = ctx.autotune(ms2.FP32, 500, 4000)
+        tuned = {f"{int(r[1])}": list(ctx.tile_config(int(r[1]), ms2.FP32, mode=1))
+                 for r in rows if r[0] == 1}
 
     # ---------------- batched form ----------------
     log(f"[bench] admitting {len(systems)} state points")
@@ -137,6 +181,8 @@ def main():
     for b in plain_batches:
         b.close()
 
+    serving = None if args.no_serve else serve_trace(args.serve_requests, args.serve_steps)
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -154,7 +200,7 @@ def main():
                    "n_range": [500, 4000], "density_range": [0.1, 0.8], "temperature_range": [1.0, 3.0],
                    "molecules": int(sum(s.n for s in systems)), "rc_over_box": 0.48,
                    "precision": "fp32 pairs, fp64 sums", "integrator": "gear-5 quaternion NVT",
-                   "moments_every": 1, "graph": True},
+                   "moments_every": 1, "graph": True, "tile_shapes_batched": tuned},
         "md_steps_per_s": steps_per_s,
         "mol_pairs_per_step": mol_pairs / K,
         "site_pairs_per_step": site_pairs / K,
@@ -167,6 +213,8 @@ def main():
                      "kernel_avg_ms": pair_ms_avg,
                      "flop_per_mol_pair": 4 * FLOP_LJ + FLOP_QQ},
     }
+    if serving is not None:
+        line["serving"] = serving
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(systems)

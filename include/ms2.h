@@ -256,7 +256,9 @@ ms2_status ms2_slot_status(ms2_batch* batch, int32_t slot, int64_t* steps_done,
                            int32_t* status, void* stream);
 
 /* Pair-kernel tile shape for n molecules: wave_rows waves of 64 molecules i
- * per block, j_chunk molecules j per work item.  The shape depends only on
+ * per block, j_chunk molecules j per work item (row-owned: every pair is
+ * evaluated from both sides), or wave_rows = 0 with j_chunk = 64: symmetric
+ * items of 64 x 64 tile pairs, every pair evaluated once.  The shape depends only on
  * the context's model class, the precision, the launch mode (0: one system
  * per launch, 1: batched) and the size bucket floor(log2 n) -- never on which
  * other systems share a launch.  Defaults are heuristic until ms2_autotune or

@@ -304,6 +304,24 @@ TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
 }
 
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits) {
+  if (c.waves == 0) {  // symmetric: tile pairs (I, J >= I) of 64 molecules
+    const int nt = (n + 63) / 64;
+    int local = 0;
+    for (int I = 0; I < nt; ++I)
+      for (int J = I; J < nt; ++J) {
+        WorkItem w{};
+        w.slot = slot;
+        w.i0 = 64 * I;
+        w.j0 = 64 * J;
+        w.j1 = std::min(n, 64 * J + 64);
+        w.part = J;
+        w.part_j = I;
+        w.local = local++;
+        out.push_back(w);
+      }
+    *jsplits = nt;
+    return local;
+  }
   const int it = 64 * c.waves;
   const int js = (n + c.jchunk - 1) / c.jchunk;
   int local = 0;
@@ -396,6 +414,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   d.jsplits = js;
   d.nitems = nitems;
   d.active = 1;
+  d.symmetric = cfg.waves == 0 ? 1 : 0;
   d.kchunks = kchunks;
   d.mchunks = mchunks;
   d.com_ld = n;
@@ -474,6 +493,7 @@ ms2_status ms2_create(ms2_ctx** out, const ms2_species* h_species, int32_t n_spe
 
 void ms2_destroy(ms2_ctx* c) {
   if (!c) return;
+  while (!c->batches.empty()) ms2_batch_destroy(c->batches.back());   // unregisters itself
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (int k = 0; k < kRing; ++k) {
@@ -505,6 +525,7 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
   RingSlot* r = nullptr;
   TileCfg cfg;
   int nitems = 0;
+  (void)hipGetLastError();   // launch checks below must not see an unrelated earlier error
   ms2_status s = single_setup(ctx, h_params, n_mol, d_species, d_com, d_quat, d_force, d_torque,
                               d_sums, false, st, &r, &cfg, &nitems);
   if (s != MS2_OK) return s;
@@ -524,6 +545,7 @@ ms2_status ms2_ewald_kspace(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_
   RingSlot* r = nullptr;
   TileCfg cfg;
   int nitems = 0;
+  (void)hipGetLastError();
   ms2_status s = single_setup(ctx, h_params, n_mol, d_species, d_com, d_quat, d_force, d_torque,
                               d_sums, true, st, &r, &cfg, &nitems);
   if (s != MS2_OK) return s;
@@ -548,9 +570,12 @@ ms2_status ms2_set_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_
                                int32_t wave_rows, int32_t j_chunk) {
   if (!ctx || n_mol < 2 || (mode != 0 && mode != 1) || (precision != MS2_FP32 && precision != MS2_FP64))
     return set_error(MS2_EINVAL, "bad arguments");
-  if (!(wave_rows == 1 || (wave_rows == 4 && ctx->cls <= 3)))
-    return set_error(MS2_EINVAL, "wave_rows must be 1 (or 4 for the first four model classes)");
-  if (j_chunk < 64 * wave_rows || j_chunk % (64 * wave_rows) != 0)
+  if (!(wave_rows == 0 || wave_rows == 1 || (wave_rows == 4 && ctx->cls <= 3)))
+    return set_error(MS2_EINVAL,
+                     "wave_rows must be 0 (symmetric), 1, or 4 (first four model classes only)");
+  if (wave_rows == 0 && j_chunk != 64)
+    return set_error(MS2_EINVAL, "symmetric tiles use j_chunk = 64");
+  if (wave_rows > 0 && (j_chunk < 64 * wave_rows || j_chunk % (64 * wave_rows) != 0))
     return set_error(MS2_EINVAL, "j_chunk must be a positive multiple of 64 * wave_rows");
   TileCfg c;
   c.waves = wave_rows;

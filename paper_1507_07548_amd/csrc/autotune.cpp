@@ -115,6 +115,12 @@ extern "C" ms2_status ms2_autotune(ms2_ctx* ctx, int32_t precision, int32_t n_lo
     make_synthetic(ctx, n, precision, syn);
     for (int mode = 0; mode <= 1; ++mode) {
       std::vector<TileCfg> cand;
+      {
+        TileCfg sym;   // symmetric 64 x 64 tile pairs
+        sym.waves = 0;
+        sym.jchunk = 64;
+        cand.push_back(sym);
+      }
       const int wmax = (mode == 1 && ctx->cls <= 3) ? 4 : 1;
       for (int w = 1; w <= wmax; w *= 4)
         for (int j = 64 * w; j <= std::max(64 * w, 2 * n); j *= 2) {

@@ -200,8 +200,14 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
   const TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
   s.waves = cfg.waves;
   s.jchunk = cfg.jchunk;   // frozen at admission: the slot's buffers are sized for it
-  s.jsplits = (s.n + cfg.jchunk - 1) / cfg.jchunk;
-  s.nitems = ((s.n + 64 * cfg.waves - 1) / (64 * cfg.waves)) * s.jsplits;
+  if (cfg.waves == 0) {    // symmetric tile pairs
+    const int nt = (s.n + 63) / 64;
+    s.jsplits = nt;
+    s.nitems = nt * (nt + 1) / 2;
+  } else {
+    s.jsplits = (s.n + cfg.jchunk - 1) / cfg.jchunk;
+    s.nitems = ((s.n + 64 * cfg.waves - 1) / (64 * cfg.waves)) * s.jsplits;
+  }
   if (sys->params.elec == MS2_ELEC_EWALD) {
     s.nk = kvec_count(sys->params.kmax2);
     s.kchunks = (s.nk + kKChunk - 1) / kKChunk;
@@ -234,7 +240,7 @@ void rebuild_items(ms2_batch* b) {
   b->max_kblocks = b->max_mchunks = b->max_mtiles = b->max_kchunks = 1;
   b->any_ewald = b->any_rdf = false;
   for (int prec : {MS2_FP64, MS2_FP32})
-    for (int waves : {1, 4}) {
+    for (int waves : {0, 1, 4}) {
       ms2_batch::Group g{prec, waves, (int)all.size(), 0};
       for (int s = 0; s < b->max_slots; ++s) {
         const SlotHost& h = b->slots[s];
@@ -337,6 +343,7 @@ ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget, 
     if (e == hipSuccess) e = hipMemcpy(b->d_md.p, zm.data(), sizeof(MDDev) * max_slots, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_prm.p, zp.data(), sizeof(SysParams) * max_slots, hipMemcpyHostToDevice);
   }
+  ctx->batches.push_back(b);
   if (e != hipSuccess) {
     ms2_batch_destroy(b);
     return hip_status(e, "ms2_batch_create");
@@ -347,6 +354,8 @@ ms2_status ms2_batch_create(ms2_ctx* ctx, int32_t max_slots, size_t hbm_budget, 
 
 void ms2_batch_destroy(ms2_batch* b) {
   if (!b) return;
+  auto& reg = b->ctx->batches;
+  reg.erase(std::remove(reg.begin(), reg.end(), b), reg.end());
   (void)hipSetDevice(b->ctx->device);
   (void)hipDeviceSynchronize();
   drop_graph(b);
@@ -373,6 +382,7 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   if (!b || !slot_out) return set_error(MS2_EINVAL, "bad arguments");
   ms2_ctx* ctx = b->ctx;
   hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
   SlotShape shape;
   ms2_status s = shape_of(ctx, sys, (b->flags & MS2_BATCH_PLAIN_TILES) ? 0 : 1, shape);
   if (s != MS2_OK) return s;
@@ -421,6 +431,7 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   d.jsplits = shape.jsplits;
   d.nitems = shape.nitems;
   d.active = 1;
+  d.symmetric = shape.waves == 0 ? 1 : 0;
   d.kchunks = shape.kchunks;
   d.mchunks = shape.mchunks;
   d.com_ld = n;
@@ -542,6 +553,7 @@ ms2_status ms2_step(ms2_batch* b, int32_t n_steps, int32_t flags, void* stream) 
   if (n_steps == 0) return MS2_OK;
   hipStream_t st = (hipStream_t)stream;
   MS2_HIP(hipSetDevice(b->ctx->device));
+  (void)hipGetLastError();
   if (b->dirty) rebuild_items(b);
   b->last_stream = st;
   bool any = false;

@@ -20,7 +20,7 @@ struct DevBuf {
 };
 
 struct TileCfg {
-  int waves = 1;    // waves per block (64 i molecules each)
+  int waves = 1;    // waves per block (64 i molecules each); 0 = symmetric tile pairs
   int jchunk = 64;  // j molecules per work item
 };
 
@@ -57,6 +57,7 @@ struct ms2_ctx {
   std::map<std::tuple<int, int, int>, ms2::TileCfg> tuned;     // (mode, precision, log2 n) -> shape
   ms2::RingSlot ring[ms2::kRing];
   int ring_pos = 0;
+  std::vector<ms2_batch*> batches;   // live batches; destroyed before the context
 };
 
 namespace ms2 {

@@ -85,7 +85,8 @@ struct SlotDev {
   int active;                 // 0: skipped by every kernel
   int kchunks, mchunks;       // Ewald force / structure-factor partial counts
   int com_ld;                 // row length of com/quat/force/torque (and slot state) arrays
-  int pad0, pad1;
+  int symmetric;              // 1: symmetric tile-pair items (each pair once)
+  int pad1;
   const int* species;
   const double* com;          // [3][com_ld]
   const double* quat;         // [4][com_ld]
@@ -111,10 +112,11 @@ __host__ __device__ inline int clamp_species(int s, int nsp) {
 }
 
 // A pair-kernel work item: molecules [i0, i0 + 64 W) of a slot against
-// j in [j0, j1); `part` selects the per-molecule partial buffer, `local` the
-// item's block-sum row within its slot.
+// j in [j0, j1); `part` selects the per-molecule partial buffer of the i
+// side, `part_j` that of the j side (symmetric items), `local` the item's
+// block-sum row within its slot.
 struct WorkItem {
-  int slot, i0, j0, j1, part, local, pad1, pad2;
+  int slot, i0, j0, j1, part, local, part_j, pad;
 };
 
 constexpr int kNumMoments = 11;   // N, X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ

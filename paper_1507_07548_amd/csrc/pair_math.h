@@ -1,0 +1,533 @@
+// Device arithmetic shared by the pair kernels (row-owned and symmetric):
+// approximate reciprocals with a Newton step, the minimum-image centre
+// difference, and the point-multipole site-pair terms.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ms2 {
+
+// FP32 reciprocal and reciprocal square root: the hardware approximations
+// (1 ulp) followed by one Newton step.  Without the step their rounding is
+// biased in one direction, and r^-6, r^-12 turn that bias into a coherent
+// relative error of the summed energy.
+template <typename Real> __device__ __forceinline__ Real rcp_(Real x);
+template <> __device__ __forceinline__ float rcp_<float>(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(y, __builtin_fmaf(-x, y, 1.0f), y);
+}
+template <> __device__ __forceinline__ double rcp_<double>(double x) { return 1.0 / x; }
+template <typename Real> __device__ __forceinline__ Real rsq_(Real x);
+template <> __device__ __forceinline__ float rsq_<float>(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float h = 0.5f * x * y;
+  return __builtin_fmaf(y, __builtin_fmaf(-h, y, 0.5f), y);
+}
+template <> __device__ __forceinline__ double rsq_<double>(double x) { return 1.0 / sqrt(x); }
+template <typename Real> __device__ __forceinline__ Real erfc_(Real x);
+template <> __device__ __forceinline__ float erfc_<float>(float x) { return erfcf(x); }
+template <> __device__ __forceinline__ double erfc_<double>(double x) { return erfc(x); }
+template <typename Real> __device__ __forceinline__ Real exp_(Real x);
+template <> __device__ __forceinline__ float exp_<float>(float x) { return expf(x); }
+template <> __device__ __forceinline__ double exp_<double>(double x) { return exp(x); }
+
+// Minimum-image centre difference, rounded exactly as written (no
+// contraction) so that the accept decision is reproducible bit for bit.
+__device__ __forceinline__ void min_image(double xi, double yi, double zi, double xj, double yj,
+                                          double zj, double L, double invL, double& dx,
+                                          double& dy, double& dz, double& r2) {
+#pragma clang fp contract(off)
+  dx = xi - xj;
+  dy = yi - yj;
+  dz = zi - zj;
+  dx = dx - L * rint(dx * invL);
+  dy = dy - L * rint(dy * invL);
+  dz = dz - L * rint(dz * invL);
+  r2 = dx * dx + dy * dy + dz * dz;
+}
+
+// ---------------------------------------------------------------------------
+// Orientation-dependent Coulomb terms of point multipoles.
+// u = K * P(ca, cb, cab) * r^-p with ca = ea.n, cb = eb.n, cab = ea.eb and n
+// the unit vector from site b (on j) to site a (on i).  P and its partial
+// derivatives (d/dca, d/dcb, d/dcab, d2/dca2, d2/dcb2, d2/dca dcb).
+// Types: 1 charge, 2 dipole, 3 quadrupole.
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct Poly {
+  Real P, Pa, Pb, Pc, Paa, Pbb, Pab;
+};
+
+template <int TA, int TB> struct MpPower;
+template <> struct MpPower<1, 2> { static constexpr int p = 2; };
+template <> struct MpPower<2, 1> { static constexpr int p = 2; };
+template <> struct MpPower<1, 3> { static constexpr int p = 3; };
+template <> struct MpPower<3, 1> { static constexpr int p = 3; };
+template <> struct MpPower<2, 2> { static constexpr int p = 3; };
+template <> struct MpPower<2, 3> { static constexpr int p = 4; };
+template <> struct MpPower<3, 2> { static constexpr int p = 4; };
+template <> struct MpPower<3, 3> { static constexpr int p = 5; };
+
+template <typename Real, int TA, int TB>
+__device__ __forceinline__ Poly<Real> mp_poly(Real ca, Real cb, Real cab) {
+  Poly<Real> q{0, 0, 0, 0, 0, 0, 0};
+  if constexpr (TA == 1 && TB == 2) {          // charge . dipole field
+    q.P = cb; q.Pb = 1;
+  } else if constexpr (TA == 2 && TB == 1) {
+    q.P = -ca; q.Pa = -1;
+  } else if constexpr (TA == 1 && TB == 3) {   // charge in a quadrupole field: P2(cb)
+    q.P = Real(1.5) * cb * cb - Real(0.5); q.Pb = Real(3) * cb; q.Pbb = Real(3);
+  } else if constexpr (TA == 3 && TB == 1) {
+    q.P = Real(1.5) * ca * ca - Real(0.5); q.Pa = Real(3) * ca; q.Paa = Real(3);
+  } else if constexpr (TA == 2 && TB == 2) {
+    q.P = cab - Real(3) * ca * cb; q.Pa = Real(-3) * cb; q.Pb = Real(-3) * ca;
+    q.Pc = 1; q.Pab = -3;
+  } else if constexpr (TA == 2 && TB == 3) {   // dipole a in the field gradient of quadrupole b
+    const Real cb2 = cb * cb;
+    q.P = Real(1.5) * ca - Real(7.5) * ca * cb2 + Real(3) * cb * cab;
+    q.Pa = Real(1.5) - Real(7.5) * cb2;
+    q.Pb = Real(3) * cab - Real(15) * ca * cb;
+    q.Pc = Real(3) * cb;
+    q.Pbb = Real(-15) * ca;
+    q.Pab = Real(-15) * cb;
+  } else if constexpr (TA == 3 && TB == 2) {
+    const Real ca2 = ca * ca;
+    q.P = Real(-1.5) * cb + Real(7.5) * ca2 * cb - Real(3) * ca * cab;
+    q.Pb = Real(-1.5) + Real(7.5) * ca2;
+    q.Pa = Real(15) * ca * cb - Real(3) * cab;
+    q.Pc = Real(-3) * ca;
+    q.Paa = Real(15) * cb;
+    q.Pab = Real(15) * ca;
+  } else {                                      // quadrupole-quadrupole
+    const Real ca2 = ca * ca, cb2 = cb * cb, cc = ca * cb;
+    q.P = Real(0.75) + Real(-3.75) * (ca2 + cb2) + Real(26.25) * ca2 * cb2 + Real(1.5) * cab * cab -
+          Real(15) * cc * cab;
+    q.Pa = Real(-7.5) * ca + Real(52.5) * ca * cb2 - Real(15) * cb * cab;
+    q.Pb = Real(-7.5) * cb + Real(52.5) * ca2 * cb - Real(15) * ca * cab;
+    q.Pc = Real(3) * cab - Real(15) * cc;
+    q.Paa = Real(-7.5) + Real(52.5) * cb2;
+    q.Pbb = Real(-7.5) + Real(52.5) * ca2;
+    q.Pab = Real(105) * cc - Real(15) * cab;
+  }
+  return q;
+}
+
+template <typename Real, int P>
+__device__ __forceinline__ Real ipow(Real x) {
+  Real r = x;
+#pragma unroll
+  for (int k = 1; k < P; ++k) r *= x;
+  return r;
+}
+
+// Per molecule-pair accumulators (Real) of the current (i, j) pair.
+template <typename Real>
+struct PairAcc {
+  Real ulj, uel, uss;
+  Real fx, fy, fz;
+};
+
+// One multipole site pair.  pa/ea: site a of i (offset, axis); pb/eb: site b
+// of j.  Adds the force on a to fs, -du/dea to gs (when a is oriented) and,
+// with JSIDE, -du/deb to gsb (when b is oriented); the force on b is -f.
+// CENTRAL: both sites at their molecules' centres, so r = R and the
+// volume-derivative terms follow from homogeneity (u ~ r^-p).
+template <typename Real, int TA, int TB, bool CENTRAL_CLASS, bool JSIDE = false>
+__device__ __forceinline__ void mp_site_pair(Real K, const Real* pa, const Real* ea, const Real* pb,
+                                             const Real* eb, Real Rx, Real Ry, Real Rz, Real R2,
+                                             PairAcc<Real>& acc, Real* fs, Real* gs, bool rf_dd,
+                                             Real krf, Real* gsb = nullptr) {
+  constexpr int p = MpPower<TA, TB>::p;
+  // the class guarantees centred dipoles/quadrupoles, not centred charges
+  constexpr bool CENTRAL = CENTRAL_CLASS && TA != 1 && TB != 1;
+  Real rx = Rx, ry = Ry, rz = Rz, r2 = R2;
+  if constexpr (!CENTRAL) {
+    rx += pa[0] - pb[0];
+    ry += pa[1] - pb[1];
+    rz += pa[2] - pb[2];
+    r2 = rx * rx + ry * ry + rz * rz;
+  }
+  const Real ir = rsq_(r2), ir2 = ir * ir;
+  const Real nx = rx * ir, ny = ry * ir, nz = rz * ir;
+  Real ca = 0, cb = 0, cab = 0;
+  if constexpr (TA != 1) ca = ea[0] * nx + ea[1] * ny + ea[2] * nz;
+  if constexpr (TB != 1) cb = eb[0] * nx + eb[1] * ny + eb[2] * nz;
+  if constexpr (TA != 1 && TB != 1) cab = ea[0] * eb[0] + ea[1] * eb[1] + ea[2] * eb[2];
+  const Poly<Real> q = mp_poly<Real, TA, TB>(ca, cb, cab);
+  const Real Kp = K * ipow<Real, p>(ir);
+  const Real u = Kp * q.P;
+  acc.uel += u;
+  // force on a = -grad_r u = (K r^-p / r) [(p P + Pa ca + Pb cb) n - Pa ea - Pb eb]
+  const Real A = Kp * ir;
+  Real sdot = Real(p) * q.P;
+  if constexpr (TA != 1) sdot += q.Pa * ca;
+  if constexpr (TB != 1) sdot += q.Pb * cb;
+  Real fx = sdot * nx, fy = sdot * ny, fz = sdot * nz;
+  if constexpr (TA != 1) { fx -= q.Pa * ea[0]; fy -= q.Pa * ea[1]; fz -= q.Pa * ea[2]; }
+  if constexpr (TB != 1) { fx -= q.Pb * eb[0]; fy -= q.Pb * eb[1]; fz -= q.Pb * eb[2]; }
+  fx *= A; fy *= A; fz *= A;
+  fs[0] += fx; fs[1] += fy; fs[2] += fz;
+  acc.fx += fx; acc.fy += fy; acc.fz += fz;
+  if constexpr (TA != 1) {
+    Real gx = q.Pa * nx, gy = q.Pa * ny, gz = q.Pa * nz;
+    if constexpr (TB != 1) { gx += q.Pc * eb[0]; gy += q.Pc * eb[1]; gz += q.Pc * eb[2]; }
+    gs[0] -= Kp * gx; gs[1] -= Kp * gy; gs[2] -= Kp * gz;
+  }
+  if constexpr (JSIDE && TB != 1) {
+    Real gx = q.Pb * nx, gy = q.Pb * ny, gz = q.Pb * nz;
+    if constexpr (TA != 1) { gx += q.Pc * ea[0]; gy += q.Pc * ea[1]; gz += q.Pc * ea[2]; }
+    gsb[0] -= Kp * gx; gsb[1] -= Kp * gy; gsb[2] -= Kp * gz;
+  }
+  if constexpr (CENTRAL) {
+    acc.uss += Real(p * (p + 1)) * u;
+  } else {
+    // second derivative of u(r + t R) at t = 0
+    const Real beta = nx * Rx + ny * Ry + nz * Rz;
+    const Real w = R2 - beta * beta;
+    Real F1 = 0, F2 = 0;
+    Real ca1 = 0, cb1 = 0;
+    if constexpr (TA != 1) {
+      ca1 = ((ea[0] * Rx + ea[1] * Ry + ea[2] * Rz) - ca * beta) * ir;
+      const Real ca2 = -(Real(2) * ca1 * beta + ca * w * ir) * ir;
+      F1 += q.Pa * ca1;
+      F2 += q.Paa * ca1 * ca1 + q.Pa * ca2;
+    }
+    if constexpr (TB != 1) {
+      cb1 = ((eb[0] * Rx + eb[1] * Ry + eb[2] * Rz) - cb * beta) * ir;
+      const Real cb2 = -(Real(2) * cb1 * beta + cb * w * ir) * ir;
+      F1 += q.Pb * cb1;
+      F2 += q.Pbb * cb1 * cb1 + q.Pb * cb2;
+    }
+    if constexpr (TA != 1 && TB != 1) F2 += Real(2) * q.Pab * ca1 * cb1;
+    const Real f1 = -Real(p) * ir * beta;
+    const Real f2 = ir2 * (Real(p * (p + 1)) * beta * beta - Real(p) * w);
+    acc.uss += Kp * (F2 + Real(2) * F1 * f1 + q.P * f2);
+  }
+  if constexpr (TA == 2 && TB == 2) {
+    if (rf_dd) {  // Barker-Watts reaction field: -2 kRF K (ea.eb); no force, no volume terms
+      acc.uel -= Real(2) * krf * K * cab;
+      gs[0] += Real(2) * krf * K * eb[0];
+      gs[1] += Real(2) * krf * K * eb[1];
+      gs[2] += Real(2) * krf * K * eb[2];
+      if constexpr (JSIDE) {
+        gsb[0] += Real(2) * krf * K * ea[0];
+        gsb[1] += Real(2) * krf * K * ea[1];
+        gsb[2] += Real(2) * krf * K * ea[2];
+      }
+    }
+  }
+}
+
+
+// Compile-time tag of a site-type pair (1 charge, 2 dipole, 3 quadrupole).
+template <int A, int B>
+struct SitePairTag {
+  static constexpr int a = A, b = B;
+};
+
+// Per-site force (and orientation-gradient) accumulators of one molecule.
+template <typename Real, int C>
+struct SiteAcc {
+  static constexpr ClassShape S = kClassShapes[C];
+  static constexpr int NLJ = S.lj > 0 ? S.lj : 1, NCH = S.ch > 0 ? S.ch : 1;
+  static constexpr int NDP = S.dp > 0 ? S.dp : 1, NQD = S.qd > 0 ? S.qd : 1;
+  Real fl[NLJ][3], fc[NCH][3], fd[NDP][3], gd[NDP][3], fq[NQD][3], gq[NQD][3];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int a = 0; a < NLJ; ++a) fl[a][c] = 0;
+#pragma unroll
+      for (int a = 0; a < NCH; ++a) fc[a][c] = 0;
+#pragma unroll
+      for (int a = 0; a < NDP; ++a) { fd[a][c] = 0; gd[a][c] = 0; }
+#pragma unroll
+      for (int a = 0; a < NQD; ++a) { fq[a][c] = 0; gq[a][c] = 0; }
+    }
+  }
+};
+
+// LDS tables of the species of one system, as the pair kernels stage them.
+template <typename Real, int C>
+struct PairTables {
+  static constexpr ClassShape S = kClassShapes[C];
+  static constexpr int NLJ = S.lj > 0 ? S.lj : 1, NCH = S.ch > 0 ? S.ch : 1;
+  static constexpr int NDP = S.dp > 0 ? S.dp : 1, NQD = S.qd > 0 ? S.qd : 1;
+  Real c6[kMaxSp * NLJ][kMaxSp * NLJ];
+  Real c12[kMaxSp * NLJ][kMaxSp * NLJ];
+  int cnt[kMaxSp][4];
+  Real mch[kMaxSp][NCH], mdp[kMaxSp][NDP], mqd[kMaxSp][NQD];   // k_e * magnitude
+  int nsite[kMaxSp][kMaxSp];
+
+  __device__ void load(const SpeciesTable* tab, const SysParams& P, int tid, int nthreads) {
+    const int nsp = P.nsp;
+    for (int e = tid; e < nsp * NLJ * nsp * NLJ; e += nthreads) {
+      const int A = e / (NLJ * nsp * NLJ), r = e % (NLJ * nsp * NLJ);
+      const int a = r / (nsp * NLJ), r2 = r % (nsp * NLJ);
+      const int B = r2 / NLJ, b = r2 % NLJ;
+      c6[A * NLJ + a][B * NLJ + b] = (Real)tab->c6[A][a][B][b];
+      c12[A * NLJ + a][B * NLJ + b] = (Real)tab->c12[A][a][B][b];
+    }
+    for (int e = tid; e < nsp; e += nthreads) {
+      const SpeciesDev& D = tab->sp[e];
+      cnt[e][0] = D.nlj; cnt[e][1] = D.nch; cnt[e][2] = D.ndp; cnt[e][3] = D.nqd;
+      for (int a = 0; a < NCH; ++a) mch[e][a] = (Real)(P.ke * D.ch_q[a]);
+      for (int a = 0; a < NDP; ++a) mdp[e][a] = (Real)(P.ke * D.dp_mu[a]);
+      for (int a = 0; a < NQD; ++a) mqd[e][a] = (Real)(P.ke * D.qd_Q[a]);
+      for (int b = 0; b < nsp; ++b) nsite[e][b] = tab->nsite_pair[e][b];
+    }
+  }
+};
+
+// Electrostatic mode constants in the pair's precision.
+template <typename Real>
+struct ElecParams {
+  int elec;
+  Real krf, crf, alpha, alpha2, gpref, inv_ke;
+};
+
+// All site pairs of one accepted molecule pair (i, j) with centre difference
+// R = R_i - R_j.  rec: the site record of i (registers); sj: the record of j,
+// component k at sj[k * STRIDE] (LDS).  Forces and orientation gradients on
+// i's sites go to ai; with JSIDE those on j's sites go to aj (force on a j
+// site is minus the force on its partner).  acc collects the pair's energy,
+// total force on i and d2U/ds2.
+template <typename Real, int C, bool JSIDE, int STRIDE>
+__device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* sj, int spi, int spj,
+                                                   const PairTables<Real, C>& T,
+                                                   const ElecParams<Real>& E, Real Rx, Real Ry,
+                                                   Real Rz, Real R2, SiteAcc<Real, C>& ai,
+                                                   SiteAcc<Real, C>& aj, PairAcc<Real>& acc) {
+  constexpr ClassShape S = kClassShapes[C];
+  constexpr int NLJ = SiteAcc<Real, C>::NLJ;
+  constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
+  constexpr bool CENTRAL = S.central != 0;
+  const int nlj_i = T.cnt[spi][0], nch_i = T.cnt[spi][1], ndp_i = T.cnt[spi][2], nqd_i = T.cnt[spi][3];
+  const int nlj_j = T.cnt[spj][0], nch_j = T.cnt[spj][1], ndp_j = T.cnt[spj][2], nqd_j = T.cnt[spj][3];
+  auto J = [&](int k) { return sj[k * STRIDE]; };
+
+  // Lennard-Jones site pairs
+#pragma unroll
+  for (int a = 0; a < S.lj; ++a) {
+    if (a >= nlj_i) break;
+#pragma unroll
+    for (int b = 0; b < S.lj; ++b) {
+      if (b >= nlj_j) break;
+      const Real rx = Rx + rec[3 * a] - J(3 * b);
+      const Real ry = Ry + rec[3 * a + 1] - J(3 * b + 1);
+      const Real rz = Rz + rec[3 * a + 2] - J(3 * b + 2);
+      const Real r2 = rx * rx + ry * ry + rz * rz;
+      const Real ir2 = rcp_(r2);
+      const Real ir6 = ir2 * ir2 * ir2;
+      const Real t6 = T.c6[spi * NLJ + a][spj * NLJ + b] * ir6;
+      const Real t12 = T.c12[spi * NLJ + a][spj * NLJ + b] * ir6 * ir6;
+      const Real dur = (Real(6) * t6 - Real(12) * t12) * ir2;       // u'/r
+      const Real d2u = (Real(156) * t12 - Real(42) * t6) * ir2;     // u''
+      const Real rR = rx * Rx + ry * Ry + rz * Rz;
+      acc.ulj += t12 - t6;
+      acc.uss += (d2u - dur) * (rR * rR * ir2) + dur * R2;
+      const Real fx = -dur * rx, fy = -dur * ry, fz = -dur * rz;
+      ai.fl[a][0] += fx; ai.fl[a][1] += fy; ai.fl[a][2] += fz;
+      if constexpr (JSIDE) { aj.fl[b][0] -= fx; aj.fl[b][1] -= fy; aj.fl[b][2] -= fz; }
+      acc.fx += fx; acc.fy += fy; acc.fz += fz;
+    }
+  }
+  // charge-charge site pairs
+  if constexpr (S.ch > 0) {
+#pragma unroll
+    for (int a = 0; a < S.ch; ++a) {
+      if (a >= nch_i) break;
+#pragma unroll
+      for (int b = 0; b < S.ch; ++b) {
+        if (b >= nch_j) break;
+        const Real K = T.mch[spi][a] * T.mch[spj][b] * E.inv_ke;
+        const Real rx = Rx + rec[OFF_CH + 3 * a] - J(OFF_CH + 3 * b);
+        const Real ry = Ry + rec[OFF_CH + 3 * a + 1] - J(OFF_CH + 3 * b + 1);
+        const Real rz = Rz + rec[OFF_CH + 3 * a + 2] - J(OFF_CH + 3 * b + 2);
+        const Real r2 = rx * rx + ry * ry + rz * rz;
+        const Real ir = rsq_(r2), ir2 = ir * ir;
+        Real u, dur, d2u;
+        if (E.elec == MS2_ELEC_EWALD) {
+          const Real r = r2 * ir;
+          const Real e = erfc_(E.alpha * r);
+          const Real gs = E.gpref * exp_(-E.alpha2 * r2);
+          u = K * e * ir;
+          dur = -K * (e * ir + gs) * ir2;
+          d2u = K * (Real(2) * e * ir * ir2 + gs * (Real(2) * ir2 + Real(2) * E.alpha2));
+        } else if (E.elec == MS2_ELEC_RF) {
+          u = K * (ir + E.krf * r2 - E.crf);
+          dur = K * (Real(2) * E.krf - ir * ir2);
+          d2u = K * (Real(2) * ir * ir2 + Real(2) * E.krf);
+        } else {
+          u = K * ir;
+          dur = -K * ir * ir2;
+          d2u = Real(2) * K * ir * ir2;
+        }
+        const Real rR = rx * Rx + ry * Ry + rz * Rz;
+        acc.uel += u;
+        acc.uss += (d2u - dur) * (rR * rR * ir2) + dur * R2;
+        const Real fx = -dur * rx, fy = -dur * ry, fz = -dur * rz;
+        ai.fc[a][0] += fx; ai.fc[a][1] += fy; ai.fc[a][2] += fz;
+        if constexpr (JSIDE) { aj.fc[b][0] -= fx; aj.fc[b][1] -= fy; aj.fc[b][2] -= fz; }
+        acc.fx += fx; acc.fy += fy; acc.fz += fz;
+      }
+    }
+  }
+  // point multipoles (all pairs involving a dipole or quadrupole)
+  if constexpr (S.dp > 0 || S.qd > 0) {
+    const bool rf_dd = E.elec == MS2_ELEC_RF;
+    const Real zero3[3] = {0, 0, 0};
+    Real gdummy[3] = {0, 0, 0};
+    auto jrec = [&](int off, Real* p) { p[0] = J(off); p[1] = J(off + 1); p[2] = J(off + 2); };
+    auto sub_f = [&](Real* dst, Real fx0, Real fy0, Real fz0) { dst[0] -= fx0; dst[1] -= fy0; dst[2] -= fz0; };
+    // each call adds the force on i's site to `fa`; the j-site force is the
+    // change of acc.f, so it is taken as a difference
+    auto pair = [&](auto ta_tb, Real K, const Real* pa, const Real* ea, const Real* pb, const Real* eb,
+                    Real* fa, Real* ga, Real* fb, Real* gb) {
+      constexpr int TA = decltype(ta_tb)::a, TB = decltype(ta_tb)::b;
+      const Real f0x = acc.fx, f0y = acc.fy, f0z = acc.fz;
+      mp_site_pair<Real, TA, TB, CENTRAL, JSIDE>(K, pa, ea, pb, eb, Rx, Ry, Rz, R2, acc, fa, ga,
+                                                  TA == 2 && TB == 2 && rf_dd, E.krf, gb);
+      if constexpr (JSIDE) sub_f(fb, acc.fx - f0x, acc.fy - f0y, acc.fz - f0z);
+    };
+    if constexpr (S.ch > 0) {
+#pragma unroll
+      for (int a = 0; a < S.ch; ++a) {
+        if (a >= nch_i) break;
+        const Real* pa = &rec[OFF_CH + 3 * a];
+        if constexpr (S.dp > 0) {
+#pragma unroll
+          for (int b = 0; b < S.dp; ++b) {
+            if (b >= ndp_j) break;
+            Real pb[3], eb[3];
+            jrec(OFF_DP + 6 * b, pb);
+            jrec(OFF_DP + 6 * b + 3, eb);
+            pair(SitePairTag<1, 2>{}, T.mch[spi][a] * T.mdp[spj][b] * E.inv_ke, pa, zero3, pb, eb, ai.fc[a], gdummy,
+                 aj.fd[b], aj.gd[b]);
+          }
+        }
+        if constexpr (S.qd > 0) {
+#pragma unroll
+          for (int b = 0; b < S.qd; ++b) {
+            if (b >= nqd_j) break;
+            Real pb[3], eb[3];
+            jrec(OFF_QD + 6 * b, pb);
+            jrec(OFF_QD + 6 * b + 3, eb);
+            pair(SitePairTag<1, 3>{}, T.mch[spi][a] * T.mqd[spj][b] * E.inv_ke, pa, zero3, pb, eb, ai.fc[a], gdummy,
+                 aj.fq[b], aj.gq[b]);
+          }
+        }
+      }
+    }
+    if constexpr (S.dp > 0) {
+#pragma unroll
+      for (int a = 0; a < S.dp; ++a) {
+        if (a >= ndp_i) break;
+        const Real* pa = &rec[OFF_DP + 6 * a];
+        const Real* ea = &rec[OFF_DP + 6 * a + 3];
+        if constexpr (S.ch > 0) {
+#pragma unroll
+          for (int b = 0; b < S.ch; ++b) {
+            if (b >= nch_j) break;
+            Real pb[3];
+            jrec(OFF_CH + 3 * b, pb);
+            pair(SitePairTag<2, 1>{}, T.mdp[spi][a] * T.mch[spj][b] * E.inv_ke, pa, ea, pb, zero3, ai.fd[a], ai.gd[a],
+                 aj.fc[b], gdummy);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < S.dp; ++b) {
+          if (b >= ndp_j) break;
+          Real pb[3], eb[3];
+          jrec(OFF_DP + 6 * b, pb);
+          jrec(OFF_DP + 6 * b + 3, eb);
+          pair(SitePairTag<2, 2>{}, T.mdp[spi][a] * T.mdp[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fd[a], ai.gd[a],
+               aj.fd[b], aj.gd[b]);
+        }
+        if constexpr (S.qd > 0) {
+#pragma unroll
+          for (int b = 0; b < S.qd; ++b) {
+            if (b >= nqd_j) break;
+            Real pb[3], eb[3];
+            jrec(OFF_QD + 6 * b, pb);
+            jrec(OFF_QD + 6 * b + 3, eb);
+            pair(SitePairTag<2, 3>{}, T.mdp[spi][a] * T.mqd[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fd[a], ai.gd[a],
+                 aj.fq[b], aj.gq[b]);
+          }
+        }
+      }
+    }
+    if constexpr (S.qd > 0) {
+#pragma unroll
+      for (int a = 0; a < S.qd; ++a) {
+        if (a >= nqd_i) break;
+        const Real* pa = &rec[OFF_QD + 6 * a];
+        const Real* ea = &rec[OFF_QD + 6 * a + 3];
+        if constexpr (S.ch > 0) {
+#pragma unroll
+          for (int b = 0; b < S.ch; ++b) {
+            if (b >= nch_j) break;
+            Real pb[3];
+            jrec(OFF_CH + 3 * b, pb);
+            pair(SitePairTag<3, 1>{}, T.mqd[spi][a] * T.mch[spj][b] * E.inv_ke, pa, ea, pb, zero3, ai.fq[a], ai.gq[a],
+                 aj.fc[b], gdummy);
+          }
+        }
+        if constexpr (S.dp > 0) {
+#pragma unroll
+          for (int b = 0; b < S.dp; ++b) {
+            if (b >= ndp_j) break;
+            Real pb[3], eb[3];
+            jrec(OFF_DP + 6 * b, pb);
+            jrec(OFF_DP + 6 * b + 3, eb);
+            pair(SitePairTag<3, 2>{}, T.mqd[spi][a] * T.mdp[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fq[a], ai.gq[a],
+                 aj.fd[b], aj.gd[b]);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < S.qd; ++b) {
+          if (b >= nqd_j) break;
+          Real pb[3], eb[3];
+          jrec(OFF_QD + 6 * b, pb);
+          jrec(OFF_QD + 6 * b + 3, eb);
+          pair(SitePairTag<3, 3>{}, T.mqd[spi][a] * T.mqd[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fq[a], ai.gq[a],
+               aj.fq[b], aj.gq[b]);
+        }
+      }
+    }
+  }
+}
+
+// Force and torque of one molecule from its per-site accumulators:
+// F = sum f, tau = sum d x f + e x g (d, e from the molecule's record, read
+// with stride STRIDE).  Accumulates into the FP64 F and T.
+template <typename Real, int C, int STRIDE>
+__device__ __forceinline__ void fold_sites(const Real* rec, const SiteAcc<Real, C>& a, double* F,
+                                           double* T) {
+  constexpr ClassShape S = kClassShapes[C];
+  constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
+  auto R = [&](int k) { return (double)rec[k * STRIDE]; };
+  auto fold = [&](int off, const Real* f) {
+    const double fx = f[0], fy = f[1], fz = f[2];
+    F[0] += fx; F[1] += fy; F[2] += fz;
+    T[0] += R(off + 1) * fz - R(off + 2) * fy;
+    T[1] += R(off + 2) * fx - R(off) * fz;
+    T[2] += R(off) * fy - R(off + 1) * fx;
+  };
+  auto fold_g = [&](int off, const Real* g) {
+    T[0] += R(off + 1) * g[2] - R(off + 2) * g[1];
+    T[1] += R(off + 2) * g[0] - R(off) * g[2];
+    T[2] += R(off) * g[1] - R(off + 1) * g[0];
+  };
+#pragma unroll
+  for (int k = 0; k < S.lj; ++k) fold(3 * k, a.fl[k]);
+#pragma unroll
+  for (int k = 0; k < S.ch; ++k) fold(OFF_CH + 3 * k, a.fc[k]);
+#pragma unroll
+  for (int k = 0; k < S.dp; ++k) { fold(OFF_DP + 6 * k, a.fd[k]); fold_g(OFF_DP + 6 * k + 3, a.gd[k]); }
+#pragma unroll
+  for (int k = 0; k < S.qd; ++k) { fold(OFF_QD + 6 * k, a.fq[k]); fold_g(OFF_QD + 6 * k + 3, a.gq[k]); }
+}
+
+}  // namespace ms2

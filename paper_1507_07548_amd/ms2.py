@@ -158,10 +158,14 @@ class Context:
         check(lib().ms2_create(ctypes.byref(h), self._arr, len(self.species), device))
         self.handle = h
         self.device = device
+        # shared with this context's batches: ms2_destroy frees every batch of
+        # the context, after which a batch must not free itself again
+        self._alive = [True]
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
-            lib().ms2_destroy(self.handle)
+            self._alive[0] = False
+            lib().ms2_destroy(self.handle)     # also destroys its remaining batches
             self.handle = None
 
     def __del__(self):
@@ -258,11 +262,12 @@ class Batch:
                                      BATCH_PLAIN_TILES if plain_tiles else 0, ctypes.byref(h)))
         self.handle = h
         self.shapes = {}
+        self._ctx_alive = ctx._alive
 
     def close(self):
-        if getattr(self, "handle", None) is not None and self.handle.value:
+        if getattr(self, "handle", None) is not None and self.handle.value and self._ctx_alive[0]:
             lib().ms2_batch_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

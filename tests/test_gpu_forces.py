@@ -214,3 +214,64 @@ def test_argument_errors_are_reported_before_launch():
     ew.elec, ew.alpha, ew.kmax2 = 2, 1.0, 10
     with pytest.raises(ms2.MS2Error):   # quadrupoles with Ewald
         ctx.forces(ew, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+
+
+# --------------------------------------------------------------------------
+# tile shapes: the work decomposition never changes the result beyond rounding
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("waves,jchunk", [(0, 64), (1, 64), (1, 192), (1, 1024), (4, 256), (4, 2048)])
+def test_tile_shape_does_not_change_the_result(waves, jchunk):
+    s = I.jittered(I.quadrupolar_fluid(n=1100, density=0.6), 0.1, seed=3)
+    ctx = ms2.Context(s.species)
+    ctx.set_tile_config(s.n, ms2.FP64, waves, jchunk, mode=0)
+    assert ctx.tile_config(s.n, ms2.FP64, mode=0) == (waves, jchunk)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, ctx=ctx, label=f"tiles {waves}x{jchunk}")
+    assert ef < 1e-11 and et < 1e-11
+    check_sums(su, so, 1e-11, 1e-12)
+
+
+@pytest.mark.parametrize("n,elec", [(2, I.ELEC_NONE), (65, I.ELEC_RF), (257, I.ELEC_RF)])
+def test_symmetric_tiles_on_every_site_type(n, elec):
+    box = 1.4 * n ** (1 / 3) + 2.5
+    s = small_system([offset_multipoles(), I.stockmayer()], n, box, 0.45 * box, seed=n + 3, elec=elec,
+                     eps_rf=25.0)
+    for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
+        ctx = ms2.Context(s.species)
+        ctx.set_tile_config(s.n, prec, 0, 64, mode=0)
+        f, t, su, fo, to, so, ef, et = compare(s, prec, ctx=ctx, label=f"symmetric offset elec={elec}")
+        assert ef < tol and et < tol, (ef, et)
+        check_sums(su, so, 1e-11 if prec == ms2.FP64 else 1e-6, 1e-12 if prec == ms2.FP64 else 1e-8)
+
+
+def test_symmetric_tiles_ewald_water_ions():
+    s = I.jittered(I.ionic_solution(), 0.3, seed=6)
+    for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 1e-5)]:
+        ctx = ms2.Context(s.species)
+        ctx.set_tile_config(s.n, prec, 0, 64, mode=0)
+        f, t, su, fo, to, so, ef, et = compare(s, prec, ctx=ctx, label="symmetric ionic")
+        assert ef < tol and et < tol, (ef, et)
+
+
+def test_symmetric_repeat_is_bitwise_identical():
+    s = I.quadrupolar_fluid(n=2000, density=0.5)
+    ctx = ms2.Context(s.species)
+    ctx.set_tile_config(s.n, ms2.FP32, 0, 64, mode=0)
+    runs = [ms2.evaluate(ctx, s, ms2.FP32) for _ in range(3)]
+    for r in runs[1:]:
+        for x, y in zip(runs[0], r):
+            assert np.array_equal(x, y)
+
+
+def test_autotuner_picks_a_valid_shape_for_every_bucket():
+    s = I.quadrupolar_fluid(n=600)
+    ctx = ms2.Context(s.species)
+    rows = ctx.autotune(ms2.FP32, 300, 1300)
+    say(f"  autotune rows {len(rows)}; best batched shapes "
+        f"{[ctx.tile_config(n, ms2.FP32, mode=1) for n in (300, 600, 1300)]}")
+    assert len(rows) > 0 and np.all(rows[:, 4] > 0)
+    for n in (300, 600, 1300):
+        for mode in (0, 1):
+            w, j = ctx.tile_config(n, ms2.FP32, mode=mode)
+            assert (w == 0 and j == 64) or (w in (1, 4) and j % (64 * w) == 0)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, ctx=ctx, label="after autotune")
+    assert ef < 1e-5

@@ -129,12 +129,16 @@ def test_gear_fp32_short_trajectory_tracks_oracle():
 # --------------------------------------------------------------------------
 # batching contract
 # --------------------------------------------------------------------------
-def test_alone_and_in_a_mix_are_bitwise_identical():
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_alone_and_in_a_mix_are_bitwise_identical(symmetric):
     a = I.quadrupolar_fluid(n=700, density=0.6, n_steps=30, sample_every=1)
     others = [I.quadrupolar_fluid(n=n, density=rho, seed=10 + n, n_steps=30, sample_every=1)
               for n, rho in [(1500, 0.4), (520, 0.75), (3000, 0.3)]]
-    say("[gpu] alone vs mix, fp32, graph")
+    say(f"[gpu] alone vs mix, fp32, graph, symmetric={symmetric}")
     ctx = ms2.Context(a.species)
+    if symmetric:
+        for n in (520, 700, 1500, 3000):
+            ctx.set_tile_config(n, ms2.FP32, 0, 64, mode=1)
     alone = ms2.Batch(ctx, 1)
     sa = alone.admit(a, ms2.FP32)
     alone.step(30)
