@@ -39,6 +39,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_label(tuned):
+    """The pair kernel(s) the batched launch used, from the tile shape per size bucket."""
+    if not tuned:
+        return "pair_kernel<float, 2CLJQ> (heuristic tile shapes)"
+    names = sorted({"pair_sym_kernel<float, 2CLJQ> (64 x 64 tile pairs, 4 waves)" if w == 0
+                    else f"pair_kernel<float, 2CLJQ, {w} wave(s)> (j chunk {j})" for w, j in tuned.values()})
+    return " + ".join(names)
+
+
 def cpu_baseline(systems, budget_s=12.0):
     """The FP64 oracle (single thread) on a bounded sample of the same state
     points: Gear NVT steps with moment sampling, site pairs per second."""
@@ -127,6 +136,9 @@ def main():
     if not args.no_autotune:
         log("[bench] autotuning tile shapes for N in [500, 4000]")
         rows = ctx.autotune(ms2.FP32, 500, 4000)
+        for r in rows:
+            shape = "symmetric 64x64" if int(r[2]) == 0 else f"{int(r[2])} wave(s), j chunk {int(r[3])}"
+            log(f"[autotune] mode {int(r[0])} n {int(r[1])}: {shape}: {r[4]:.2f} us/system")
         tuned = {f"{int(r[1])}": list(ctx.tile_config(int(r[1]), ms2.FP32, mode=1))
                  for r in rows if r[0] == 1}
 
@@ -209,7 +221,7 @@ def main():
         "batched_over_plain": value / plain_value,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-                     "kernel": "pair_kernel<float, 2CLJQ, 4 waves>",
+                     "kernel": kernel_label(tuned),
                      "kernel_avg_ms": pair_ms_avg,
                      "flop_per_mol_pair": 4 * FLOP_LJ + FLOP_QQ},
     }

@@ -115,6 +115,20 @@ __device__ __forceinline__ void block_sums(double (*s_red)[NT], const double* v,
   if (tid < kNumBlockSums) out[tid] = s_red[tid][0];
 }
 
+// Sums of v[k] over the 64 lanes of a wave in butterfly order (a fixed
+// order; every lane ends with the same bits); lane k writes out[k].
+__device__ __forceinline__ void wave_sums(double* v, double* out) {
+#pragma unroll
+  for (int h = 32; h > 0; h >>= 1) {
+#pragma unroll
+    for (int k = 0; k < kNumBlockSums; ++k) v[k] += __shfl_xor(v[k], h, 64);
+  }
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kNumBlockSums; ++k)
+    if (lane == k) out[k] = v[k];
+}
+
 template <typename Real, int C, int W>
 __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict__ items,
                                                       int item_base,
@@ -128,7 +142,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
   __shared__ int s_sp[TJ];
   __shared__ Real s_site[NR][TJ];
   __shared__ PairTables<Real, C> s_tab;
-  __shared__ double s_red[kNumBlockSums][TJ];
+  __shared__ double s_red[W > 1 ? kNumBlockSums : 1][W > 1 ? TJ : 1];
 
   const WorkItem it = items[item_base + blockIdx.x];
   const SlotDev& sd = slots[it.slot];
@@ -228,151 +242,303 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
     pf[0 * np + i] = F[0]; pf[1 * np + i] = F[1]; pf[2 * np + i] = F[2];
     pf[3 * np + i] = T[0]; pf[4 * np + i] = T[1]; pf[5 * np + i] = T[2];
   }
-  const double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
-  block_sums<TJ>(s_red, v, sd.bsum + (size_t)it.local * kNumBlockSums);
+  double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
+  if constexpr (W > 1)
+    block_sums<TJ>(s_red, v, sd.bsum + (size_t)it.local * kNumBlockSums);
+  else
+    wave_sums(v, sd.bsum + (size_t)it.local * kNumBlockSums);
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric pair kernel: work items are 64 x 64 tile pairs (I, J >= I); every
-// accepted pair is evaluated once.  The lane owning i keeps i's side in
-// registers; the reaction force and torque on j go to LDS accumulators of the
-// j tile (hardware LDS float adds; one wave per block, so only this wave
-// updates them).  Partials: molecule m of tile T receives exactly one partial
-// per tile index p -- the j side of item (p, T) for p < T, the i side of item
-// (T, p) for p > T, and both sides of the diagonal item (T, T) for p = T --
-// so the fixed-order reduction over p is unchanged.
+// Symmetric pair kernel: work items are 64 x 64 tile pairs (I, J >= I) and
+// every accepted molecule pair is evaluated once, by one lane, with no
+// atomics.  Four waves share one item (its tiles are staged once).
+//  1. the cut-off bits of the 64 x 64 pairs (FP64, j > i on the diagonal
+//     tile; each wave tests 16 columns of every row) are rotated right by
+//     the row index l, so that bit d marks pair (l, l + d): "diagonal" d of
+//     the tile.  Ballots transpose the rows into one 64-bit word per
+//     diagonal (each wave 16 of them); a wave scan of their counts gives
+//     each diagonal's offset in the diagonal-major list of accepted pairs.
+//  2. the list is processed 64 entries at a time, one pair per lane, the
+//     chunks dealt to the waves in turn.  For each diagonal of a chunk (a
+//     scalar walk over the offsets finds them), lane m holds row m's entry
+//     index: the diagonal's offset plus the count of set bits below bit m
+//     (mbcnt).  Lanes write their (row, diagonal) to those slots of a
+//     per-wave list, from which each lane reads its pair.
+//  3. each lane stages its pair's force and torques in its wave's LDS area.
+//     Lane m then gathers the entries of molecule m of tile I (as a row, at
+//     its own entry index) and of tile J (as a column, at the index held by
+//     lane m - d): on each diagonal d of the chunk there is at most one of
+//     each.  Sums stay in registers; there are no read-modify-writes of
+//     shared memory.
+//  4. the reaction on j follows from the pair's force and torque on i:
+//     F_j = -F_i and, the pair energy being invariant under a rigid rotation
+//     of both molecules, tau_j = -tau_i - R x F_i with R = R_i - R_j.
+//  5. the four waves' partials are added in wave order.
+// The schedule and the order of additions depend on the tile's data only.
+// Partials: molecule m of tile T receives exactly one partial per tile index
+// p -- the column side of item (p, T) for p < T, the row side of item (T, p)
+// for p > T, and both sides of the diagonal item (T, T) -- so the
+// fixed-order reduction over p is unchanged.
 // ---------------------------------------------------------------------------
-template <typename Real, int C>
-__global__ __launch_bounds__(64) void pair_sym_kernel(const WorkItem* __restrict__ items,
-                                                      int item_base,
-                                                      const SlotDev* __restrict__ slots,
-                                                      const SysParams* __restrict__ prm,
-                                                      const SpeciesTable* __restrict__ tab) {
-  constexpr ClassShape S = kClassShapes[C];
-  constexpr int NR = class_reals(C);
-  constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
-  constexpr int TJ = 64;
+constexpr int kSymWaves = 4;
 
-  __shared__ double s_com[3][TJ];
-  __shared__ int s_sp[TJ];
-  __shared__ Real s_site[NR][TJ];
+// Index in the chunk [q, q + 64) of this lane's row on a diagonal with word
+// wd starting at offset o - q (all wave-uniform), or -1 if the row is not on
+// it or its entry lies outside the chunk.
+__device__ __forceinline__ int row_entry(unsigned long long wd, int o_rel, int lane) {
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(wd >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)wd, 0u));
+  const int e = o_rel + rank;
+  const bool on = ((wd >> lane) & 1ull) != 0ull;
+  return (on && e >= 0 && e < 64) ? e : -1;
+}
+
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Orders this wave's LDS accesses before and after (the wave's lanes only).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <typename Real, int NR>
+struct SymTiles {
+  double com[2][3][64];                 // [rows, columns][xyz][molecule]
+  Real site[2][NR][64];
+  Real stage[kSymWaves][9][64];         // F_i, tau_i, tau_j of each lane's pair
+};
+
+template <typename Real>
+struct SymFinal {
+  Real part[kSymWaves][12][64];         // per wave: row F, tau; column F, tau
+  double sums[kSymWaves][kNumBlockSums];
+};
+
+template <typename Real, int C>
+__global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem* __restrict__ items,
+                                                                  int item_base,
+                                                                  const SlotDev* __restrict__ slots,
+                                                                  const SysParams* __restrict__ prm,
+                                                                  const SpeciesTable* __restrict__ tab) {
+  constexpr int NR = class_reals(C);
+  constexpr int TJ = 64, NW = kSymWaves;
+
+  __shared__ union {
+    SymTiles<Real, NR> t;
+    SymFinal<Real> f;
+  } u;
+  __shared__ int s_sp[2][TJ];
   __shared__ PairTables<Real, C> s_tab;
-  __shared__ Real s_accj[6][TJ];
-  __shared__ double s_red[kNumBlockSums][TJ];
+  __shared__ unsigned s_mpart[NW][TJ];
+  __shared__ unsigned long long s_dw[TJ];
+  __shared__ int s_list[NW][TJ];          // per wave: row | diagonal << 6 of each entry of the chunk
 
   const WorkItem it = items[item_base + blockIdx.x];
   const SlotDev& sd = slots[it.slot];
   if (!sd.active) return;
   const SysParams& P = prm[it.slot];
-  const int tid = threadIdx.x;
+  // wave index made explicitly wave-uniform, so that the chunk loop and
+  // the walks over diagonals run on scalar registers
+  const int tid = threadIdx.x, lane = tid & (TJ - 1), wv = __builtin_amdgcn_readfirstlane(tid / TJ);
   const int nsp = P.nsp;
-  s_tab.load(tab, P, tid, TJ);
+  s_tab.load(tab, P, tid, TJ * NW);
 
   const int n = sd.n, ld = sd.com_ld, np = sd.npad;
   const double L = P.L, invL = P.invL, rc2 = P.rc2;
   const ElecParams<Real> E = elec_params<Real>(P);
   const Real* __restrict__ gsite = reinterpret_cast<const Real*>(sd.sites);
   const bool diag = it.i0 == it.j0;
+  const int nrow = min(TJ, n - it.i0), ncol = min(TJ, n - it.j0);
 
-  const int i = it.i0 + tid;
-  const bool iv = i < n;
-  const int ic = iv ? i : 0;
-  const double xi = sd.com[ic], yi = sd.com[ld + ic], zi = sd.com[2 * ld + ic];
-  const int spi = iv ? clamp_species(sd.species[ic], nsp) : 0;
-  Real rec[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) rec[k] = gsite[k * np + ic];
   {
-    const int j = it.j0 + tid;
-    const bool jv = j < n;
-    const int jc = jv ? j : 0;
-    s_com[0][tid] = sd.com[jc];
-    s_com[1][tid] = sd.com[ld + jc];
-    s_com[2][tid] = sd.com[2 * ld + jc];
-    s_sp[tid] = jv ? clamp_species(sd.species[jc], nsp) : 0;
+    // stage both tiles: waves 0/1 the centres and species of rows/columns,
+    // waves 2/3 their site records; every global load before the LDS stores
+    const int side = wv & 1;
+    const int base = side ? it.j0 : it.i0, cnt = side ? ncol : nrow;
+    const int mc = lane < cnt ? base + lane : 0;
+    if (wv < 2) {
+      double c3[3];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) s_site[k][tid] = gsite[k * np + jc];
+      for (int c = 0; c < 3; ++c) c3[c] = sd.com[c * ld + mc];
+      const int sp = lane < cnt ? clamp_species(sd.species[mc], nsp) : 0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s_accj[c][tid] = 0;
+      for (int c = 0; c < 3; ++c) u.t.com[side][c][lane] = c3[c];
+      s_sp[side][lane] = sp;
+    } else {
+      Real r[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) r[k] = gsite[k * np + mc];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) u.t.site[side][k][lane] = r[k];
+    }
+    s_list[wv][lane] = 0;
   }
   __syncthreads();
 
-  // phase 1: cut-off bits (diagonal tile: j > i only)
-  const int nvalid = min(TJ, n - it.j0);
-  const int iself = i - it.j0;
-  unsigned long long m = 0;
-  for (int jj = 0; jj < TJ; ++jj) {
-    double dx, dy, dz, r2;
-    min_image(xi, yi, zi, s_com[0][jj], s_com[1][jj], s_com[2][jj], L, invL, dx, dy, dz, r2);
-    const unsigned ok = (unsigned)(r2 < rc2) & (unsigned)(jj < nvalid) & (unsigned)(!diag || jj > iself);
-    m |= (unsigned long long)ok << jj;
+  // 1. cut-off bits: wave wv tests columns [16 wv, 16 wv + 16) of row `lane`
+  {
+    const double xi = u.t.com[0][0][lane], yi = u.t.com[0][1][lane], zi = u.t.com[0][2][lane];
+    unsigned part = 0;
+    for (int b = 0; b < 16; ++b) {
+      const int jj = 16 * wv + b;
+      double dx, dy, dz, r2;
+      min_image(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L, invL, dx, dy, dz,
+                r2);
+      const unsigned ok = (unsigned)(r2 < rc2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
+      part |= ok << b;
+    }
+    s_mpart[wv][lane] = lane < nrow ? part : 0u;
   }
-  if (!iv) m = 0ull;
+  __syncthreads();
+  // row masks rotated so that bit d is column lane + d; wave wv transposes
+  // diagonals [16 wv, 16 wv + 16)
+  {
+    unsigned long long m = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) m |= (unsigned long long)s_mpart[w][lane] << (16 * w);
+    m = lane == 0 ? m : ((m >> lane) | (m << (TJ - lane)));
+    for (int b = 0; b < 16; ++b) {
+      const int d = 16 * wv + b;
+      const unsigned long long w = __builtin_amdgcn_ballot_w64(((m >> d) & 1ull) != 0ull);
+      if (lane == b) s_dw[d] = w;
+    }
+  }
+  __syncthreads();
+  const unsigned long long dword = s_dw[lane];   // lane d: the pairs (l, l + d) of every row l
+  const int cnt = __popcll(dword);
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < TJ; o <<= 1) {
+    const int t = __shfl_up(incl, o, TJ);
+    if (lane >= o) incl += t;
+  }
+  const int doff = incl - cnt;               // lane d: offset of diagonal d
+  const int total = __builtin_amdgcn_readlane(incl, TJ - 1);
 
+  // 2.-3. the diagonal-major list, one pair per lane, chunks dealt to waves
   double a_ulj = 0, a_uel = 0, a_us = 0, a_uss = 0;
   int a_np = 0, a_ns = 0;
-  SiteAcc<Real, C> ai, aj;
-  ai.zero();
-  // phase 2: accepted pairs of this lane, each evaluated once
-  while (m) {
-    const int jj = __builtin_ctzll(m);
-    m &= m - 1ull;
-    const int spj = s_sp[jj];
+  Real g_row[6] = {0, 0, 0, 0, 0, 0}, g_col[6] = {0, 0, 0, 0, 0, 0};
+  Real(*stage)[TJ] = u.t.stage[wv];
+  int dfirst = 0;                            // wave-uniform
+  int* list = s_list[wv];
+  for (int q = wv * TJ; q < total; q += NW * TJ) {
+    const bool valid = q + lane < total;
+    const int qend = min(q + TJ, total);
+    // the chunk's diagonals: from the one holding entry q to the last one
+    // starting before the chunk's end (wave-uniform)
+    while (dfirst < TJ - 1 && __builtin_amdgcn_readlane(doff, dfirst + 1) <= q) ++dfirst;
+    int dlast = dfirst;
+    while (dlast < TJ - 1 && __builtin_amdgcn_readlane(doff, dlast + 1) < qend) ++dlast;
+    for (int dd = dfirst; dd <= dlast; ++dd) {
+      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q, lane);
+      if (er >= 0) list[er] = lane | (dd << 6);
+    }
+    wave_sync_lds();
+    const int pr = list[lane];
+    const int row = pr & (TJ - 1);
+    const int col = (row + (pr >> 6)) & (TJ - 1);
+
+    const int spi = s_sp[0][row], spj = s_sp[1][col];
     double dx, dy, dz, r2d;
-    min_image(xi, yi, zi, s_com[0][jj], s_com[1][jj], s_com[2][jj], L, invL, dx, dy, dz, r2d);
+    min_image(u.t.com[0][0][row], u.t.com[0][1][row], u.t.com[0][2][row], u.t.com[1][0][col],
+              u.t.com[1][1][col], u.t.com[1][2][col], L, invL, dx, dy, dz, r2d);
     const Real Rx = (Real)dx, Ry = (Real)dy, Rz = (Real)dz;
     const Real R2 = Rx * Rx + Ry * Ry + Rz * Rz;
-    PairAcc<Real> acc{0, 0, 0, 0, 0, 0};
-    aj.zero();
-    eval_molecule_pair<Real, C, true, TJ>(rec, &s_site[0][jj], spi, spj, s_tab, E, Rx, Ry, Rz, R2, ai, aj,
-                                          acc);
-    // reaction on j: -F_ij and tau_j = sum_b d_b x f_b + e_b x g_b
-    double Fj[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
-    fold_sites<Real, C, TJ>(&s_site[0][jj], aj, Fj, Tj);
-    atomicAdd(&s_accj[0][jj], (Real)Fj[0]);
-    atomicAdd(&s_accj[1][jj], (Real)Fj[1]);
-    atomicAdd(&s_accj[2][jj], (Real)Fj[2]);
-    atomicAdd(&s_accj[3][jj], (Real)Tj[0]);
-    atomicAdd(&s_accj[4][jj], (Real)Tj[1]);
-    atomicAdd(&s_accj[5][jj], (Real)Tj[2]);
-    a_ulj += (double)acc.ulj;
-    a_uel += (double)acc.uel;
-    a_uss += (double)acc.uss;
-    a_us -= (double)(Rx * acc.fx + Ry * acc.fy + Rz * acc.fz);
-    a_np += 1;
-    a_ns += s_tab.nsite[spi][spj];
-  }
-  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  fold_sites<Real, C, 1>(rec, ai, F, T);
-  __syncthreads();
-  double G[6];
+    Real rec[NR];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) G[c] = (double)s_accj[c][tid];
-  if (diag) {
-    if (iv) {
-      double* pf = sd.pf + (size_t)it.part * 6 * np;
-      for (int c = 0; c < 3; ++c) {
-        pf[c * np + i] = F[c] + G[c];
-        pf[(3 + c) * np + i] = T[c] + G[3 + c];
+    for (int k = 0; k < NR; ++k) rec[k] = u.t.site[0][k][row];
+    PairAcc<Real> acc{0, 0, 0, 0, 0, 0};
+    SiteAcc<Real, C> ai, unused;
+    ai.zero();
+    eval_molecule_pair<Real, C, false, TJ>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry, Rz, R2,
+                                           ai, unused, acc);
+    Real Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0};
+    fold_sites<Real, C, 1, Real>(rec, ai, Fi, Ti);
+    if (valid) {
+      a_ulj += (double)acc.ulj;
+      a_uel += (double)acc.uel;
+      a_uss += (double)acc.uss;
+      a_us -= (double)(Rx * acc.fx + Ry * acc.fy + Rz * acc.fz);
+      a_np += 1;
+      a_ns += s_tab.nsite[spi][spj];
+    }
+    stage[0][lane] = Fi[0];
+    stage[1][lane] = Fi[1];
+    stage[2][lane] = Fi[2];
+    stage[3][lane] = Ti[0];
+    stage[4][lane] = Ti[1];
+    stage[5][lane] = Ti[2];
+    stage[6][lane] = -Ti[0] - (Ry * Fi[2] - Rz * Fi[1]);
+    stage[7][lane] = -Ti[1] - (Rz * Fi[0] - Rx * Fi[2]);
+    stage[8][lane] = -Ti[2] - (Rx * Fi[1] - Ry * Fi[0]);
+    wave_sync_lds();
+    // gather: molecule `lane` of tile I at its own entry index; molecule
+    // `lane` of tile J is the column of row lane - dd
+    for (int dd = dfirst; dd <= dlast; ++dd) {
+      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q, lane);
+      const int ec = __shfl(er, (lane - dd) & (TJ - 1), TJ);
+      if (er >= 0) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) g_row[c] += stage[c][er];
+      }
+      if (ec >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          g_col[c] -= stage[c][ec];
+          g_col[3 + c] += stage[6 + c][ec];
+        }
       }
     }
-  } else {
-    if (iv) {
-      double* pf = sd.pf + (size_t)it.part * 6 * np;
-      for (int c = 0; c < 3; ++c) {
-        pf[c * np + i] = F[c];
-        pf[(3 + c) * np + i] = T[c];
-      }
-    }
-    const int j = it.j0 + tid;
-    if (tid < nvalid) {
-      double* pf = sd.pf + (size_t)it.part_j * 6 * np;
-      for (int c = 0; c < 6; ++c) pf[c * np + j] = G[c];
-    }
+    wave_sync_lds();
   }
-  (void)OFF_QD;
-  const double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
-  block_sums<TJ>(s_red, v, sd.bsum + (size_t)it.local * kNumBlockSums);
+
+  // 5. the waves' partials, added in wave order
+  double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
+  __syncthreads();                           // tiles and stages are dead from here
+  wave_sums(v, u.f.sums[wv]);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    u.f.part[wv][c][lane] = g_row[c];
+    u.f.part[wv][6 + c][lane] = g_col[c];
+  }
+  __syncthreads();
+  if (wv == 0) {
+    double fr[6], fc[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      fr[c] = (double)u.f.part[0][c][lane];
+      fc[c] = (double)u.f.part[0][6 + c][lane];
+    }
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        fr[c] += (double)u.f.part[w][c][lane];
+        fc[c] += (double)u.f.part[w][6 + c][lane];
+      }
+    double* pf_i = sd.pf + (size_t)it.part * 6 * np;
+    if (diag) {
+      if (lane < nrow)
+        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = fr[c] + fc[c];
+    } else {
+      double* pf_j = sd.pf + (size_t)it.part_j * 6 * np;
+      if (lane < nrow)
+        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = fr[c];
+      if (lane < ncol)
+        for (int c = 0; c < 6; ++c) pf_j[c * np + it.j0 + lane] = fc[c];
+    }
+  } else if (wv == 1 && lane < kNumBlockSums) {
+    double t = u.f.sums[0][lane];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) t += u.f.sums[w][lane];
+    sd.bsum[(size_t)it.local * kNumBlockSums + lane] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -509,8 +675,8 @@ static hipError_t launch_pair_c(int waves, const WorkItem* items, int base, int 
                                 const SpeciesTable* tab, hipStream_t st) {
   if (waves == 0) {  // symmetric tile pairs
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((pair_sym_kernel<Real, C>), dim3(count), dim3(64), 0, st, items, base, slots, prm,
-                       tab);
+    hipLaunchKernelGGL((pair_sym_kernel<Real, C>), dim3(count), dim3(64 * kSymWaves), 0, st, items, base,
+                       slots, prm, tab);
     return hipGetLastError();
   }
   if constexpr (C <= 3) {

@@ -501,24 +501,23 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
 
 // Force and torque of one molecule from its per-site accumulators:
 // F = sum f, tau = sum d x f + e x g (d, e from the molecule's record, read
-// with stride STRIDE).  Accumulates into the FP64 F and T.
-template <typename Real, int C, int STRIDE>
-__device__ __forceinline__ void fold_sites(const Real* rec, const SiteAcc<Real, C>& a, double* F,
-                                           double* T) {
+// with stride STRIDE).  Accumulates into F and T, of type Out.
+template <typename Real, int C, int STRIDE, typename Out = double>
+__device__ __forceinline__ void fold_sites(const Real* rec, const SiteAcc<Real, C>& a, Out* F, Out* T) {
   constexpr ClassShape S = kClassShapes[C];
   constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
-  auto R = [&](int k) { return (double)rec[k * STRIDE]; };
+  auto R = [&](int k) { return (Out)rec[k * STRIDE]; };
   auto fold = [&](int off, const Real* f) {
-    const double fx = f[0], fy = f[1], fz = f[2];
+    const Out fx = f[0], fy = f[1], fz = f[2];
     F[0] += fx; F[1] += fy; F[2] += fz;
     T[0] += R(off + 1) * fz - R(off + 2) * fy;
     T[1] += R(off + 2) * fx - R(off) * fz;
     T[2] += R(off) * fy - R(off + 1) * fx;
   };
   auto fold_g = [&](int off, const Real* g) {
-    T[0] += R(off + 1) * g[2] - R(off + 2) * g[1];
-    T[1] += R(off + 2) * g[0] - R(off) * g[2];
-    T[2] += R(off) * g[1] - R(off + 1) * g[0];
+    T[0] += R(off + 1) * (Out)g[2] - R(off + 2) * (Out)g[1];
+    T[1] += R(off + 2) * (Out)g[0] - R(off) * (Out)g[2];
+    T[2] += R(off) * (Out)g[1] - R(off + 1) * (Out)g[0];
   };
 #pragma unroll
   for (int k = 0; k < S.lj; ++k) fold(3 * k, a.fl[k]);
