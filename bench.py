@@ -104,6 +104,49 @@ def serve_trace(n_requests, n_steps):
             "note": "scaled trace: the full request asks 2e4 steps and a 1000-step ACF window"}
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pair_sym_kernel_hbm_traffic.md")
+
+
+def recorded_traffic():
+    """HBM bytes per batched pair-kernel launch from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    from paper_1507_07548_amd.rocprof_summary import pair_kernel_source_hash
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    for ln in open(TRAFFIC_SUMMARY):
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].strip().split(": ", 1)
+            fields[k] = v.strip("` ")
+    if fields.get("source_sha256") != pair_kernel_source_hash():
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
+def plain_form(ms2, torch, ctx, sample, K, W):
+    """One system per launch, no graph, plain tile shapes."""
+    log(f"[bench] plain form on {len(sample)} systems")
+    batches = []
+    for s in sample:
+        b = ms2.Batch(ctx, 1, plain_tiles=True)
+        b.admit(s, ms2.FP32)
+        b.step(W if W > 0 else 1, graph=False)
+        batches.append(b)
+    torch.cuda.synchronize()
+    pb = [b.sample(0, state=False) for b in batches]
+    t0 = time.perf_counter()
+    for b in batches:
+        b.step(K, graph=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pa = [b.sample(0, state=False) for b in batches]
+    sp = sum(a["site_pairs_total"] - b["site_pairs_total"] for a, b in zip(pa, pb))
+    for b in batches:
+        b.close()
+    return {"value": sp / (t1 - t0), "md_steps_per_s": len(sample) * K / (t1 - t0), "systems": len(sample),
+            "form": "one system per launch, no graph, plain tile shapes"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,24 +159,42 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=400)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the batched steps directly instead of through a hipGraph")
+    ap.add_argument("--tile-shape", type=str, default=None,
+                    help="waves,jchunk for every size bucket instead of autotuning (0,64 = symmetric)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs each system on a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1507_07548_amd import inputs, ms2
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     K, W = args.steps, args.warmup
+    graph = not args.no_graph
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {nbytes} bytes device to device (counter calibration)")
+        del src, dst
     systems = [inputs.batched_state_point(s) for s in range(args.systems)]
     ctx = ms2.Context(systems[0].species)
-    stream = torch.cuda.current_stream()
     tuned = None
-    if not args.no_autotune:
+    if args.tile_shape:
+        w, j = (int(x) for x in args.tile_shape.split(","))
+        for b in range(8, 13):                       # size buckets floor(log2 N) of N in [500, 4000]
+            ctx.set_tile_config(1 << b, ms2.FP32, w, j, mode=1)
+        tuned = {str(1 << b): [w, j] for b in range(8, 13)}
+    elif not args.no_autotune:
         log("[bench] autotuning tile shapes for N in [500, 4000]")
         rows = ctx.autotune(ms2.FP32, 500, 4000)
         for r in rows:
@@ -147,14 +208,15 @@ def main():
     batch = ms2.Batch(ctx, len(systems))
     slots = [batch.admit(s, ms2.FP32) for s in systems]
     if W > 0:
-        batch.step(W, graph=True)
-    batch.step(K, graph=True, timing=True, prepare=True)        # capture + instantiate, no run
+        batch.step(W, graph=graph)
+    if graph:
+        batch.step(K, graph=True, timing=True, prepare=True)    # capture + instantiate, no run
     torch.cuda.synchronize()
     before = [batch.sample(s, state=False) for s in slots]
     log(f"[bench] timing {K} batched steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    batch.step(K, graph=True, timing=True)
+    batch.step(K, graph=graph, timing=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     after = [batch.sample(s, state=False) for s in slots]
@@ -170,29 +232,8 @@ def main():
     achieved = flops_per_launch / (pair_ms_avg * 1e-3)
     batch.close()
 
-    # ---------------- plain form: one system per launch, no graph ----------------
     sample = systems[: args.plain_sample]
-    log(f"[bench] plain form on {len(sample)} systems")
-    plain_batches = []
-    for s in sample:
-        b = ms2.Batch(ctx, 1, plain_tiles=True)
-        b.admit(s, ms2.FP32)
-        b.step(W if W > 0 else 1, graph=False)
-        plain_batches.append(b)
-    torch.cuda.synchronize()
-    pb = [b.sample(0, state=False) for b in plain_batches]
-    t0 = time.perf_counter()
-    for b in plain_batches:
-        b.step(K, graph=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pa = [b.sample(0, state=False) for b in plain_batches]
-    plain_sp = sum(a["site_pairs_total"] - b["site_pairs_total"] for a, b in zip(pa, pb))
-    plain_value = plain_sp / (t1 - t0)
-    plain_steps = len(sample) * K / (t1 - t0)
-    for b in plain_batches:
-        b.close()
-
+    plain = plain_form(ms2, torch, ctx, sample, K, W) if sample else None
     serving = None if args.no_serve else serve_trace(args.serve_requests, args.serve_steps)
 
     line = {
@@ -212,19 +253,19 @@ def main():
                    "n_range": [500, 4000], "density_range": [0.1, 0.8], "temperature_range": [1.0, 3.0],
                    "molecules": int(sum(s.n for s in systems)), "rc_over_box": 0.48,
                    "precision": "fp32 pairs, fp64 sums", "integrator": "gear-5 quaternion NVT",
-                   "moments_every": 1, "graph": True, "tile_shapes_batched": tuned},
+                   "moments_every": 1, "graph": graph, "tile_shapes_batched": tuned},
         "md_steps_per_s": steps_per_s,
         "mol_pairs_per_step": mol_pairs / K,
         "site_pairs_per_step": site_pairs / K,
-        "plain": {"value": plain_value, "md_steps_per_s": plain_steps, "systems": len(sample),
-                  "form": "one system per launch, no graph, plain tile shapes"},
-        "batched_over_plain": value / plain_value,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": recorded_traffic(),
                      "kernel": kernel_label(tuned),
                      "kernel_avg_ms": pair_ms_avg,
                      "flop_per_mol_pair": 4 * FLOP_LJ + FLOP_QQ},
     }
+    if plain is not None:
+        line["plain"] = plain
+        line["batched_over_plain"] = value / plain["value"]
     if serving is not None:
         line["serving"] = serving
     if not args.no_cpu_baseline:

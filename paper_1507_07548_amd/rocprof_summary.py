@@ -1,7 +1,34 @@
-"""Writes a short per-kernel summary (calls, average and total duration) from
-a rocprofv3 --kernel-trace results database (`*_results.db`)."""
+"""Short text summaries of rocprofv3 output.
+
+  kernels <results.db> [kernel substring]
+      per-kernel calls, average and total duration from a --kernel-trace
+      results database; with a substring, also the average duration of that
+      kernel's largest-grid (batched) launches.
+  traffic <fetch.csv> <write.csv> <copy_bytes> <kernel substring>
+      HBM bytes per launch of the largest-grid dispatches whose name holds
+      the substring, from two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+      dispatch).  Each counter is scaled by bytes / counter of the largest
+      device-to-device copy in the same run (a copy of copy_bytes bytes reads
+      and writes exactly that many).  Prints the fields bench.py reads.
+"""
+import csv
+import hashlib
+import os
 import sqlite3
 import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PAIR_SOURCES = ["csrc/forces.hip", "csrc/pair_math.h", "csrc/internal.h"]
+
+
+def pair_kernel_source_hash():
+    """sha256 over the sources of the pair kernels (a changed kernel voids
+    counters taken before the change)."""
+    h = hashlib.sha256()
+    for rel in PAIR_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def summarize(db_path, top=12):
@@ -15,5 +42,77 @@ def summarize(db_path, top=12):
     return "\n".join(out)
 
 
+def largest_grid(db_path, substring):
+    """Calls and average duration (us) of the largest-grid dispatches of the
+    kernels whose name holds the substring (the batched launches)."""
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select grid_x * grid_y * grid_z, duration from kernels where name like ?",
+                       (f"%{substring}%",)).fetchall()
+    if not rows:
+        raise SystemExit(f"no dispatch of a kernel named like {substring!r}")
+    gmax = max(g for g, _ in rows)
+    d = [t for g, t in rows if g == gmax]
+    return len(d), sum(d) / len(d) / 1e3, gmax
+
+
+def _dispatches(csv_path, counter):
+    """{dispatch id: (kernel name, grid size, counter value)}"""
+    out = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            d = out.get(r["Dispatch_Id"])
+            v = float(r["Counter_Value"]) + (d[2] if d else 0.0)
+            out[r["Dispatch_Id"]] = (r["Kernel_Name"], int(r["Grid_Size"]), v)
+    return out
+
+
+def _per_launch(disp, substring):
+    hits = [(g, v, n) for n, g, v in disp.values() if substring in n]
+    if not hits:
+        raise SystemExit(f"no dispatch of a kernel named like {substring!r}")
+    gmax = max(g for g, _, _ in hits)
+    vals = [v for g, v, _ in hits if g == gmax]
+    return sum(vals) / len(vals), len(vals), hits[0][2].split("(")[0]
+
+
+def _copy_kib(disp):
+    copies = [v for n, g, v in disp.values() if "copy" in n.lower()]
+    if not copies:
+        raise SystemExit("no copy kernel in the run: pass --copy-calibration-mib to bench.py")
+    return max(copies)
+
+
+def traffic(fetch_csv, write_csv, copy_bytes, substring):
+    fd, wd = _dispatches(fetch_csv, "FETCH_SIZE"), _dispatches(write_csv, "WRITE_SIZE")
+    f_kib, nf, name = _per_launch(fd, substring)
+    w_kib, nw, _ = _per_launch(wd, substring)
+    cf, cw = _copy_kib(fd), _copy_kib(wd)
+    sf, sw = copy_bytes / cf, copy_bytes / cw            # bytes per counter unit, per direction
+    total = f_kib * sf + w_kib * sw
+    lines = [
+        f"Kernel `{name}`: {nf} (FETCH_SIZE) and {nw} (WRITE_SIZE) batched launches.",
+        "",
+        "| | counter per launch (KiB) | copy of known size (KiB) | bytes per unit | HBM bytes per launch |",
+        "|---|---|---|---|---|",
+        f"| FETCH_SIZE | {f_kib:.1f} | {cf:.1f} | {sf:.2f} | {f_kib * sf:.4g} |",
+        f"| WRITE_SIZE | {w_kib:.1f} | {cw:.1f} | {sw:.2f} | {w_kib * sw:.4g} |",
+        "",
+        f"- hbm_bytes_per_launch: {total:.6g}",
+        f"- source_sha256: `{pair_kernel_source_hash()}`",
+    ]
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
-    print(summarize(sys.argv[1]))
+    if len(sys.argv) >= 2 and sys.argv[1] == "traffic":
+        print(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5]))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "kernels":
+        print(summarize(sys.argv[2]))
+        if len(sys.argv) >= 4:
+            n, avg, g = largest_grid(sys.argv[2], sys.argv[3])
+            print(f"\nLargest-grid launches of `{sys.argv[3]}` (grid {g} work-items): {n} calls, "
+                  f"average {avg:.1f} us.")
+    else:
+        print(summarize(sys.argv[1]))
