@@ -422,7 +422,8 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   d.com = d_com;
   d.quat = d_quat;
   d.sites = ctx->s_sites.p;
-  d.pf = (double*)ctx->s_pf.p;
+  d.pf = ctx->s_pf.p;
+  d.pf_single = p->precision == MS2_FP32 ? 1 : 0;
   d.bsum = (double*)ctx->s_bsum.p;
   d.force = d_force;
   d.torque = d_torque;

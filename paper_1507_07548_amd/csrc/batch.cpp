@@ -79,7 +79,7 @@ SlotLayout layout_of(const SlotShape& s) {
   const size_t n = s.n, np = s.npad, rs = s.precision == MS2_FP32 ? 4 : 8;
   L.species = take(n * 4);
   L.sites = take((size_t)class_reals(s.cls) * np * rs);
-  L.pf = take((size_t)s.jsplits * 6 * np * 8);
+  L.pf = take((size_t)s.jsplits * 6 * np * rs);
   L.bsum = take((size_t)s.nitems * kNumBlockSums * 8);
   L.force = take(3 * n * 8);
   L.torque = take(3 * n * 8);
@@ -439,7 +439,8 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   d.com = (const double*)(base + lay.r);
   d.quat = (const double*)(base + lay.q);
   d.sites = base + lay.sites;
-  d.pf = (double*)(base + lay.pf);
+  d.pf = base + lay.pf;
+  d.pf_single = shape.precision == MS2_FP32 ? 1 : 0;
   d.bsum = (double*)(base + lay.bsum);
   d.force = (double*)(base + lay.force);
   d.torque = (double*)(base + lay.torque);

@@ -238,9 +238,9 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
   }
 
   if (iv) {
-    double* pf = sd.pf + (size_t)it.part * 6 * np;
-    pf[0 * np + i] = F[0]; pf[1 * np + i] = F[1]; pf[2 * np + i] = F[2];
-    pf[3 * np + i] = T[0]; pf[4 * np + i] = T[1]; pf[5 * np + i] = T[2];
+    Real* pf = reinterpret_cast<Real*>(sd.pf) + (size_t)it.part * 6 * np;
+    pf[0 * np + i] = (Real)F[0]; pf[1 * np + i] = (Real)F[1]; pf[2 * np + i] = (Real)F[2];
+    pf[3 * np + i] = (Real)T[0]; pf[4 * np + i] = (Real)T[1]; pf[5 * np + i] = (Real)T[2];
   }
   double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
   if constexpr (W > 1)
@@ -522,16 +522,16 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
         fr[c] += (double)u.f.part[w][c][lane];
         fc[c] += (double)u.f.part[w][6 + c][lane];
       }
-    double* pf_i = sd.pf + (size_t)it.part * 6 * np;
+    Real* pf_i = reinterpret_cast<Real*>(sd.pf) + (size_t)it.part * 6 * np;
     if (diag) {
       if (lane < nrow)
-        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = fr[c] + fc[c];
+        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = (Real)(fr[c] + fc[c]);
     } else {
-      double* pf_j = sd.pf + (size_t)it.part_j * 6 * np;
+      Real* pf_j = reinterpret_cast<Real*>(sd.pf) + (size_t)it.part_j * 6 * np;
       if (lane < nrow)
-        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = fr[c];
+        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = (Real)fr[c];
       if (lane < ncol)
-        for (int c = 0; c < 6; ++c) pf_j[c * np + it.j0 + lane] = fc[c];
+        for (int c = 0; c < 6; ++c) pf_j[c * np + it.j0 + lane] = (Real)fc[c];
     }
   } else if (wv == 1 && lane < kNumBlockSums) {
     double t = u.f.sums[0][lane];
@@ -544,7 +544,9 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
 // ---------------------------------------------------------------------------
 // Fixed-order reductions of the pair partials.
 //  reduce_force_kernel: one thread per molecule sums its j-range partials in
-//    order; grid (molecule blocks, slots).  OVERWRITES force and torque.
+//    order, in FP64 (the partials are in the slot's Real: each is a sum of at
+//    most one tile's pair terms); grid (molecule blocks, slots).  OVERWRITES
+//    force and torque.
 //  reduce_sums_kernel: one block per slot; item sums (each thread a
 //    contiguous run, then a tree), species counts, Ewald constants and the LJ
 //    tail.  OVERWRITES sums.
@@ -556,9 +558,17 @@ __global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __rest
   if (i >= sd.n) return;
   const int np = sd.npad, ld = sd.com_ld;
   double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int p = 0; p < sd.jsplits; ++p)
+  if (sd.pf_single) {
+    const float* pf = reinterpret_cast<const float*>(sd.pf);
+    for (int p = 0; p < sd.jsplits; ++p)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] += sd.pf[((size_t)p * 6 + c) * np + i];
+      for (int c = 0; c < 6; ++c) v[c] += (double)pf[((size_t)p * 6 + c) * np + i];
+  } else {
+    const double* pf = reinterpret_cast<const double*>(sd.pf);
+    for (int p = 0; p < sd.jsplits; ++p)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] += pf[((size_t)p * 6 + c) * np + i];
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     sd.force[c * ld + i] = v[c];

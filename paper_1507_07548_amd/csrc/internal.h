@@ -86,12 +86,12 @@ struct SlotDev {
   int kchunks, mchunks;       // Ewald force / structure-factor partial counts
   int com_ld;                 // row length of com/quat/force/torque (and slot state) arrays
   int symmetric;              // 1: symmetric tile-pair items (each pair once)
-  int pad1;
+  int pf_single;              // 1: pair partials in FP32 (the FP32 form), 0: FP64
   const int* species;
   const double* com;          // [3][com_ld]
   const double* quat;         // [4][com_ld]
   void* sites;                // [class_reals][npad] Real
-  double* pf;                 // [jsplits][6][npad] pair partial F, tau
+  void* pf;                   // [jsplits][6][npad] pair partial F, tau, in the slot's Real
   double* bsum;               // [nitems][kNumBlockSums]
   double* force;              // [3][com_ld]
   double* torque;             // [3][com_ld]
