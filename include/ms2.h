@@ -278,6 +278,40 @@ ms2_status ms2_set_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_
 ms2_status ms2_autotune(ms2_ctx* ctx, int32_t precision, int32_t n_lo, int32_t n_hi,
                         double* h_report, int32_t max_report, int32_t* n_report, void* stream);
 
+/* Residual Massieu-potential derivatives (Sec. 3, Eq. 1):
+ * A^r_mn = beta^m rho^n d^(m+n)(F^r/(N k T)) / d beta^m d rho^n, beta = 1/T,
+ * rho = N/V, for the eight (m, n) the paper samples, from the moment sums of
+ * one NVT run (ms2_samples.moments, shifted by u0 as in ms2_system.u0).
+ * Molecular scaling: centres scale with the box, bodies stay rigid.  The
+ * estimators are the canonical fluctuation formulas of
+ * phi = ln INT exp(-beta U(s; V)) ds over the sampled configurations:
+ * cumulants of U, dU/dV, d2U/dV2 up to third order.
+ *   h_moments    host [11] sums (count, X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ)
+ *   u0           the shift X = U - u0 used while sampling
+ *   temperature  k T (energy units of U), volume V, n_mol N
+ *   h_ar         host [MS2_NAR] out, order MS2_AR_10 ... MS2_AR_12
+ * Host arithmetic only (no device work).  MS2_EINVAL on a null pointer, no
+ * samples, or a non-positive temperature, volume or N. */
+enum { MS2_AR_10 = 0, MS2_AR_01, MS2_AR_20, MS2_AR_11, MS2_AR_02, MS2_AR_30, MS2_AR_21, MS2_AR_12,
+       MS2_NAR };
+ms2_status ms2_massieu(const double* h_moments, double u0, double temperature, double volume,
+                       int32_t n_mol, double* h_ar);
+
+/* Properties per molecule (k = 1) from A_mn = A^i_mn + A^r_mn, the ideal part
+ * of classical rigid molecules with `dof` quadratic degrees of freedom
+ * (3 translational + 0, 2 or 3 rotational): A^i_10 = dof/2, A^i_20 = -dof/2,
+ * A^i_30 = dof, A^i_01 = 1, A^i_02 = -1, the mixed ones 0 (Sec. 3: for n > 0
+ * the ideal part depends on the density only).
+ *   h_ar     host [MS2_NAR] residual derivatives (ms2_massieu)
+ *   h_props  host [MS2_NPROP] out: p/(rho k T); u/(k T); c_v/k; c_p/k;
+ *            (dp/drho)_T/(k T); (dp/dT)_rho/(rho k); w^2 m/(k T) (speed of
+ *            sound, m = molecular mass); rho k T kappa_T (isothermal
+ *            compressibility)
+ * MS2_EINVAL on a null pointer or dof <= 0. */
+enum { MS2_PROP_Z = 0, MS2_PROP_U_KT, MS2_PROP_CV, MS2_PROP_CP, MS2_PROP_DPDRHO, MS2_PROP_DPDT,
+       MS2_PROP_W2, MS2_PROP_KAPPA_T, MS2_NPROP };
+ms2_status ms2_massieu_properties(const double* h_ar, double dof, double* h_props);
+
 /* Thread-local message of the last failed call ("" if none). */
 const char* ms2_last_error(void);
 

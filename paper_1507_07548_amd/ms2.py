@@ -77,7 +77,8 @@ _lib = None
 EXPORTED = ["ms2_create", "ms2_destroy", "ms2_forces", "ms2_ewald_kspace", "ms2_batch_create",
             "ms2_batch_destroy", "ms2_slot_footprint", "ms2_slot_admit", "ms2_slot_retire",
             "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_set_tile_config",
-            "ms2_autotune", "ms2_batch_timing", "ms2_last_error"]
+            "ms2_autotune", "ms2_batch_timing", "ms2_massieu", "ms2_massieu_properties",
+            "ms2_last_error"]
 
 
 def lib():
@@ -106,6 +107,8 @@ def lib():
         L.ms2_tile_config.argtypes = [vp, c_int32, c_int32, c_int32, P(c_int32), P(c_int32)]
         L.ms2_set_tile_config.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, c_int32]
         L.ms2_autotune.argtypes = [vp, c_int32, c_int32, c_int32, P(c_double), c_int32, P(c_int32), vp]
+        L.ms2_massieu.argtypes = [dp, c_double, c_double, c_double, c_int32, dp]
+        L.ms2_massieu_properties.argtypes = [dp, c_double, dp]
         L.ms2_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name not in ("ms2_destroy", "ms2_batch_destroy", "ms2_last_error"):
@@ -341,3 +344,28 @@ class Batch:
         for k, v in arrays.items():
             res[k] = v.T.copy() if k in ("com", "quat", "vel", "omega", "force", "torque") else v
         return res
+
+
+# --------------------------------------------------------------------------
+# Massieu-potential derivatives (Sec. 3, Eq. 1)
+# --------------------------------------------------------------------------
+AR_ORDER = ("10", "01", "20", "11", "02", "30", "21", "12")
+PROP_ORDER = ("Z", "u_kT", "cv_k", "cp_k", "dpdrho_kT", "dpdT_rhok", "w2_m_kT", "rho_kT_kappaT")
+
+
+def massieu(moments, u0: float, temperature: float, volume: float, n_mol: int) -> dict:
+    """The eight residual derivatives A^r_mn from a slot's moment sums."""
+    m = (c_double * 11)(*[float(x) for x in moments])
+    out = (c_double * 8)()
+    check(lib().ms2_massieu(m, float(u0), float(temperature), float(volume), int(n_mol), out))
+    return dict(zip(AR_ORDER, list(out)))
+
+
+def massieu_properties(a_r: dict, dof: float) -> dict:
+    """Thermodynamic properties per molecule (k = 1) from the residual
+    derivatives and the ideal part of rigid molecules with `dof` quadratic
+    degrees of freedom."""
+    a = (c_double * 8)(*[float(a_r[k]) for k in AR_ORDER])
+    out = (c_double * 8)()
+    check(lib().ms2_massieu_properties(a, float(dof), out))
+    return dict(zip(PROP_ORDER, list(out)))
