@@ -643,6 +643,85 @@ static void acf_sample(acf_t* A, int s, const double* vel, const or_species* sp,
   }
 }
 
+/* Residence time and solvation number (Sec. 5, Eqs. 7-8).  A solvent
+ * molecule k belongs to the shell of solute i while their centres are closer
+ * than the radius.  At every time origin (the ACF origins) the molecules in
+ * each solute's shell are recorded; at a later sample, molecule k still
+ * counts for that origin while it is in the shell, unless it has at some
+ * point been outside for more than `tol` consecutive samples (the allowance
+ * of Impey et al. for short excursions).  The correlation at a lag is the
+ * counted fraction of the shell at the origin. */
+typedef struct {
+  int on, tol, nlag, every, origin_every, max_live, n_origins;
+  int nu, nv;
+  int* solute;         /* molecule indices of the central molecules      */
+  int* solvent;        /* molecule indices of the counted molecules      */
+  double r2;
+  int* t0;             /* [max_live] origin steps                         */
+  int* n0;             /* [max_live][nu] shell population at the origin   */
+  int* away;           /* [max_live][nu][nv]: -1 = does not count for this
+                          origin, else consecutive samples spent outside  */
+} res_t;
+
+static int in_shell(const res_t* R, const double* com, double L, int i, int k) {
+  if (i == k) return 0;
+  double d[3];
+  for (int c = 0; c < 3; ++c) {
+    d[c] = com[3 * i + c] - com[3 * k + c];
+    d[c] = d[c] - L * rint(d[c] / L);
+  }
+  double r2 = d[0] * d[0];
+  r2 = r2 + d[1] * d[1];
+  r2 = r2 + d[2] * d[2];
+  return r2 < R->r2;
+}
+
+static void residence_sample(res_t* R, int s, const double* com, double L, double* res_acf,
+                             double* res_cnt, double* solvation) {
+  int nu = R->nu, nv = R->nv;
+  if (solvation) {
+    for (int a = 0; a < nu; ++a)
+      for (int b = 0; b < nv; ++b) solvation[0] += in_shell(R, com, L, R->solute[a], R->solvent[b]);
+    solvation[1] += nu;
+  }
+  if (s % R->origin_every == 0) {
+    int o = R->n_origins % R->max_live;
+    R->t0[o] = s;
+    for (int a = 0; a < nu; ++a) {
+      int pop = 0;
+      for (int b = 0; b < nv; ++b) {
+        int in = in_shell(R, com, L, R->solute[a], R->solvent[b]);
+        R->away[((size_t)o * nu + a) * nv + b] = in ? 0 : -1;
+        pop += in;
+      }
+      R->n0[(size_t)o * nu + a] = pop;
+    }
+    R->n_origins++;
+  }
+  int live = R->n_origins < R->max_live ? R->n_origins : R->max_live;
+  for (int o = 0; o < live; ++o) {
+    if (s < R->t0[o]) continue;
+    int lag = (s - R->t0[o]) / R->every;
+    if (lag >= R->nlag) continue;
+    for (int a = 0; a < nu; ++a) {
+      int pop0 = R->n0[(size_t)o * nu + a];
+      if (pop0 == 0) continue;
+      int resident = 0;
+      for (int b = 0; b < nv; ++b) {
+        int* w = &R->away[((size_t)o * nu + a) * nv + b];
+        int in = in_shell(R, com, L, R->solute[a], R->solvent[b]);
+        if (lag > 0 && *w >= 0) {
+          *w = in ? 0 : *w + 1;
+          if (*w > R->tol) *w = -1;
+        }
+        if (*w >= 0 && in) resident++;
+      }
+      if (res_acf) res_acf[lag] += (double)resident / (double)pop0;
+      if (res_cnt) res_cnt[lag] += 1.0;
+    }
+  }
+}
+
 /* RDF histogram between all LJ sites (Sec. 5, Eq. 2): unordered site pairs of
  * distinct molecules, site distance from the minimum-image centre shift;
  * bin = (int)(r * bins / rmax). */
@@ -708,7 +787,7 @@ static void wrap_box(double* x, int n3, double L) {
 int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg* cfg,
           int32_t n, const int32_t* species, double* com, double* quat, double* vel,
           double* omega, double* energy_log, double* moments, double* rdf, double* acf_v,
-          double* acf_j, double* acf_cnt) {
+          double* acf_j, double* acf_cnt, double* res_acf, double* res_cnt, double* solvation) {
   int e = or_check(sp, nsp, p);
   if (e) return e;
   if (!cfg || n < 2 || cfg->n_steps < 0 || !(cfg->dt > 0.0)) return -30;
@@ -739,6 +818,31 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
     acf.v0 = calloc((size_t)acf.max_live * n3, sizeof(double));
     acf.j0 = calloc((size_t)acf.max_live * 3, sizeof(double));
   }
+  res_t res;
+  memset(&res, 0, sizeof(res));
+  if (cfg->res_solute >= 0) {
+    if (cfg->acf_every <= 0 || cfg->res_solute >= nsp || cfg->res_solvent < 0 || cfg->res_solvent >= nsp ||
+        !(cfg->res_radius > 0.0) || !(cfg->res_radius < 0.5 * p->box) || cfg->res_tolerance < 0) {
+      free(F); free(Tq); free(acf.t0); free(acf.v0); free(acf.j0);
+      return -34;
+    }
+    res.on = 1;
+    res.tol = cfg->res_tolerance;
+    res.nlag = cfg->acf_nlag;
+    res.every = cfg->acf_every;
+    res.origin_every = cfg->acf_origin_every;
+    res.max_live = acf.max_live;
+    res.r2 = cfg->res_radius * cfg->res_radius;
+    res.solute = malloc(sizeof(int) * (size_t)n);
+    res.solvent = malloc(sizeof(int) * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+      if (species[i] == cfg->res_solute) res.solute[res.nu++] = i;
+      if (species[i] == cfg->res_solvent) res.solvent[res.nv++] = i;
+    }
+    res.t0 = calloc((size_t)res.max_live, sizeof(int));
+    res.n0 = calloc((size_t)res.max_live * (res.nu + 1), sizeof(int));
+    res.away = calloc((size_t)res.max_live * (res.nu + 1) * (res.nv + 1), sizeof(int));
+  }
   /* translational and rotational degrees of freedom (isokinetic NVT) */
   double f_tr = 3.0 * n - 3.0, f_rot = 0.0;
   for (int i = 0; i < n; ++i)
@@ -758,6 +862,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
       energy_log[3] = sums[OR_VIRIAL];
     }
     if (acf.n) acf_sample(&acf, 0, vel, sp, species, acf_v, acf_j, acf_cnt);
+    if (res.on) residence_sample(&res, 0, com, L, res_acf, res_cnt, solvation);
     for (int s = 1; s <= cfg->n_steps; ++s) {
       for (int i = 0; i < n; ++i) {
         double m = sp[species[i]].mass;
@@ -790,6 +895,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
       if (rdf && cfg->rdf_every > 0 && s % cfg->rdf_every == 0)
         rdf_sample(sp, nsp, p, cfg, n, species, com, quat, rdf);
       if (acf.n && s % cfg->acf_every == 0) acf_sample(&acf, s, vel, sp, species, acf_v, acf_j, acf_cnt);
+      if (res.on && s % cfg->acf_every == 0) residence_sample(&res, s, com, L, res_acf, res_cnt, solvation);
     }
     goto done;
   }
@@ -834,6 +940,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
       energy_log[3] = sums[OR_VIRIAL];
     }
     if (acf.n) acf_sample(&acf, 0, vel, sp, species, acf_v, acf_j, acf_cnt);
+    if (res.on) residence_sample(&res, 0, com, L, res_acf, res_cnt, solvation);
 
     for (int s = 1; s <= cfg->n_steps && !e; ++s) {
       gear_predict(r, (int)n3);
@@ -908,6 +1015,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
         for (size_t c = 0; c < n3; ++c) vtmp[c] = r[1][c] / dt;
         acf_sample(&acf, s, vtmp, sp, species, acf_v, acf_j, acf_cnt);
       }
+      if (res.on && s % cfg->acf_every == 0) residence_sample(&res, s, r[0], L, res_acf, res_cnt, solvation);
     }
     memcpy(com, r[0], n3 * sizeof(double));
     memcpy(quat, q[0], n4 * sizeof(double));
@@ -919,5 +1027,6 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
 done:
   free(F); free(Tq);
   free(acf.t0); free(acf.v0); free(acf.j0);
+  free(res.solute); free(res.solvent); free(res.t0); free(res.n0); free(res.away);
   return e;
 }

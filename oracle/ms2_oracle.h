@@ -89,6 +89,13 @@ typedef struct {
   int32_t acf_nlag;         /* lags per origin (window / n)             */
   double rdf_rmax;
   double u0;                /* shift of U inside the moment sums        */
+  int32_t res_solute;       /* residence time (Sec. 5, Eqs. 7-8): species of
+                               the central molecules, -1 = off          */
+  int32_t res_solvent;      /* species counted around them              */
+  double res_radius;        /* shell radius between molecule centres    */
+  int32_t res_tolerance;    /* samples a molecule may stay outside and
+                               still count as resident                  */
+  int32_t res_pad;
 } or_md_cfg;
 
 /* moments[] slots: sums over samples of powers and products of
@@ -120,12 +127,18 @@ int or_kspace(const or_species* sp, int32_t nsp, const or_params* p,
  * rdf[npairtypes*rdf_bins] (counts as doubles, unordered site pairs);
  * acf_v[acf_nlag], acf_j[acf_nlag], acf_cnt[acf_nlag]: raw sums over
  * origins of (1/N) sum_i v_i(t0).v_i(t0+l n), of j_e(t0).j_e(t0+l n), and
- * the number of origins contributing to each lag.  Any output may be NULL. */
+ * the number of origins contributing to each lag.  Residence sampling (on
+ * the ACF schedule): res_acf[acf_nlag] sums over (origin, solute with a
+ * non-empty shell at the origin) of the fraction of its initial shell still
+ * resident, res_cnt[acf_nlag] the number of such terms, solvation[2] = (sum
+ * over samples and solutes of the shell population, number of terms).  Any
+ * output may be NULL. */
 int or_md(const or_species* sp, int32_t nsp, const or_params* p,
           const or_md_cfg* cfg, int32_t n, const int32_t* species,
           double* com, double* quat, double* vel, double* omega,
           double* energy_log, double* moments, double* rdf,
-          double* acf_v, double* acf_j, double* acf_cnt);
+          double* acf_v, double* acf_j, double* acf_cnt,
+          double* res_acf, double* res_cnt, double* solvation);
 
 /* Number of LJ site types (one per LJ site of each species) used by the
  * RDF; histograms are stored for every unordered type pair (t1 <= t2). */
