@@ -166,6 +166,14 @@ typedef struct {
   int32_t acf_nlag;          /* lags per origin                            */
   double rdf_rmax;
   double u0;                 /* energy shift inside the moment sums        */
+  int32_t res_enable;        /* 1: residence time and solvation number
+                                (Sec. 5, Eqs. 7-8), sampled with the ACFs;
+                                0: off (a zero-filled struct samples none) */
+  int32_t res_solute;        /* species of the central molecules           */
+  int32_t res_solvent;       /* species of the molecules counted around them */
+  int32_t res_tolerance;     /* samples a molecule may spend outside the shell
+                                and still count as resident (Impey et al.) */
+  double res_radius;         /* shell radius between molecule centres (< box/2) */
   const int32_t* h_species;  /* [n]    */
   const double* h_com;       /* [3][n] */
   const double* h_quat;      /* [4][n] */
@@ -234,10 +242,17 @@ typedef struct {
   double moments[11];        /* sums of X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ
                                 (slot 0 = number of samples); X = U - u0,
                                 Y = dU/dV, Z = d2U/dV2                     */
+  double solvation_sum;      /* sum over samples and solutes of the number of
+                                solvent molecules inside the shell         */
+  double solvation_cnt;      /* number of (sample, solute) terms in it     */
   double* h_rdf;             /* [npairtypes][rdf_bins] counts, or NULL     */
   double* h_acf_v;           /* [acf_nlag] sum over origins of (1/N) sum v(t0).v(t0+l n) */
   double* h_acf_j;           /* [acf_nlag] sum over origins of j_e(t0).j_e(t0+l n) */
   double* h_acf_cnt;         /* [acf_nlag] origins per lag                 */
+  double* h_res_acf;         /* [acf_nlag] sum over (origin, solute) with a
+                                non-empty shell at t0 of the fraction of its
+                                initial shell still resident at lag l      */
+  double* h_res_cnt;         /* [acf_nlag] number of those terms per lag   */
   double* h_com;             /* optional [3][n] current state              */
   double* h_quat;            /* optional [4][n]                            */
   double* h_vel;             /* optional [3][n]                            */
@@ -248,7 +263,14 @@ typedef struct {
 
 /* Copies a slot's accumulated samples and (optionally) its state to host
  * memory; synchronizes `stream`.  Lustig moments (Sec. 3, Eq. 1), RDF
- * (Sec. 5, Eq. 2), velocity and electric-current ACFs (Sec. 5, Eqs. 3-4). */
+ * (Sec. 5, Eq. 2), velocity and electric-current ACFs (Sec. 5, Eqs. 3-4),
+ * residence-time correlation and solvation-number sums (Sec. 5, Eqs. 7-8).
+ * Residence: at a time origin t0 every solvent molecule inside the shell of
+ * a solute is tracked; it counts at lag l while inside the shell, unless it
+ * has been outside for more than res_tolerance consecutive samples since t0
+ * (then it never counts again for that origin).  tau = (sum of the lag means
+ * of h_res_acf / h_res_cnt) x acf_every x dt by the trapezoid rule; the
+ * solvation number is solvation_sum / solvation_cnt. */
 ms2_status ms2_sample(ms2_batch* batch, int32_t slot, ms2_samples* h_out, void* stream);
 
 /* Per-slot progress without copying samples: steps done, status. */

@@ -36,6 +36,8 @@ hipError_t launch_md_init(SlotDev* slots, MDDev* md, const SpeciesTable* tab, in
                           hipStream_t st);
 hipError_t launch_md_begin(const SlotDev* slots, MDDev* md, const SysParams* prm,
                            const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
+hipError_t launch_residence(const SlotDev* slots, MDDev* md, const SysParams* prm, int slot_base,
+                            int nslots, int max_solute, hipStream_t st);
 hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const SpeciesTable* tab,
                          int nslots, hipStream_t st);
 hipError_t launch_rdf(int waves, const WorkItem* items, int base, int count, const SlotDev* slots,
@@ -58,12 +60,14 @@ struct SlotLayout {
   size_t species, sites, pf, bsum, force, torque, sums, r, q, w, vel;
   size_t skp, sk, fk, kred, ksum, moments, rdf, acf_v, acf_j, acf_cnt, origin_v, origin_j,
       origin_t0;
+  size_t res_idx, res_state, res_n0, res_part, res_inside, res_acf, res_cnt;
   size_t total;
 };
 
 struct SlotShape {
   int n, npad, cls, precision, jsplits, nitems, waves, jchunk, mode, nk, kchunks, mchunks, mtiles;
   int rdf_ntp, rdf_bins, acf_nlag, acf_max_live;
+  int n_solute, n_solvent;   // residence sampling (0 = off)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -101,6 +105,14 @@ SlotLayout layout_of(const SlotShape& s) {
   L.origin_v = take((size_t)s.acf_max_live * 3 * n * 8);
   L.origin_j = take((size_t)s.acf_max_live * 3 * 8);
   L.origin_t0 = take((size_t)s.acf_max_live * 8);
+  const size_t nu = s.n_solute, nv = s.n_solvent, ml = s.n_solute ? s.acf_max_live : 0;
+  L.res_idx = take((nu + nv) * 4);
+  L.res_state = take(ml * nu * nv * 2);
+  L.res_n0 = take(ml * nu * 4);
+  L.res_part = take(nu * ml * 8);
+  L.res_inside = take(nu * 4);
+  L.res_acf = take(s.n_solute ? (size_t)s.acf_nlag * 8 : 0);
+  L.res_cnt = take(s.n_solute ? (size_t)s.acf_nlag * 8 : 0);
   L.total = off;
   return L;
 }
@@ -144,7 +156,8 @@ struct ms2_batch {
   std::vector<Group> groups;
   bool dirty = true;
   int max_n = 2, max_kblocks = 1, max_mchunks = 1, max_mtiles = 1, max_kchunks = 1;
-  bool any_ewald = false, any_rdf = false;
+  bool any_ewald = false, any_rdf = false, any_res = false;
+  int max_solute = 0;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_steps = 0, graph_flags = 0;
@@ -230,6 +243,23 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
     s.acf_nlag = sys->acf_nlag;
     s.acf_max_live = (int)((long long)sys->acf_nlag * sys->acf_every / sys->acf_origin_every + 2);
   }
+  if (sys->res_enable) {
+    if (sys->acf_every <= 0) return set_error(MS2_EINVAL, "residence sampling runs on the ACF schedule: acf_every > 0");
+    if (sys->res_solute < 0 || sys->res_solute >= ctx->tab.nsp || sys->res_solvent < 0 ||
+        sys->res_solvent >= ctx->tab.nsp)
+      return set_error(MS2_EINVAL, "residence solute/solvent species out of range");
+    if (!(sys->res_radius > 0.0) || !(sys->res_radius < 0.5 * sys->params.box) || sys->res_tolerance < 0 ||
+        sys->res_tolerance >= (int)kResDead - 1)
+      return set_error(MS2_EINVAL, "residence needs 0 < radius < box/2 and 0 <= tolerance < 65534");
+    if (s.acf_max_live > kResMaxLive)
+      return set_error(MS2_EINVAL, "too many live ACF origins for residence sampling");
+    for (int i = 0; i < s.n; ++i) {
+      s.n_solute += sys->h_species[i] == sys->res_solute;
+      s.n_solvent += sys->h_species[i] == sys->res_solvent;
+    }
+    if (s.n_solute == 0 || s.n_solvent == 0)
+      return set_error(MS2_EINVAL, "residence solute or solvent species absent from the system");
+  }
   return MS2_OK;
 }
 
@@ -238,7 +268,8 @@ void rebuild_items(ms2_batch* b) {
   b->groups.clear();
   b->max_n = 2;
   b->max_kblocks = b->max_mchunks = b->max_mtiles = b->max_kchunks = 1;
-  b->any_ewald = b->any_rdf = false;
+  b->any_ewald = b->any_rdf = b->any_res = false;
+  b->max_solute = 0;
   for (int prec : {MS2_FP64, MS2_FP32})
     for (int waves : {0, 1, 4}) {
       ms2_batch::Group g{prec, waves, (int)all.size(), 0};
@@ -266,6 +297,10 @@ void rebuild_items(ms2_batch* b) {
       b->max_kchunks = std::max(b->max_kchunks, h.shape.kchunks);
     }
     if (h.md.rdf_every > 0) b->any_rdf = true;
+    if (h.shape.n_solute > 0) {
+      b->any_res = true;
+      b->max_solute = std::max(b->max_solute, h.shape.n_solute);
+    }
   }
   if (!all.empty()) {
     (void)b->d_items.ensure(all.size() * sizeof(WorkItem));
@@ -310,6 +345,7 @@ ms2_status enqueue_step(ms2_batch* b, hipStream_t st, int timed_step) {
     for (auto& g : b->groups)
       MS2_HIP(launch_rdf(g.waves, (const WorkItem*)b->d_items.p, g.begin, g.end - g.begin, ds, dm, dp,
                          ctx->d_tab, st));
+  if (b->any_res) MS2_HIP(launch_residence(ds, dm, dp, 0, b->max_slots, b->max_solute, st));
   return MS2_OK;
 }
 
@@ -501,6 +537,28 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   m.origin_v = (double*)(base + lay.origin_v);
   m.origin_j = (double*)(base + lay.origin_j);
   m.origin_t0 = (long long*)(base + lay.origin_t0);
+  std::vector<int> res_idx;
+  if (shape.n_solute > 0) {
+    for (int i = 0; i < n; ++i)
+      if (sys->h_species[i] == sys->res_solute) res_idx.push_back(i);
+    for (int i = 0; i < n; ++i)
+      if (sys->h_species[i] == sys->res_solvent) res_idx.push_back(i);
+    m.res_on = 1;
+    m.res_tol = sys->res_tolerance;
+    m.n_solute = shape.n_solute;
+    m.n_solvent = shape.n_solvent;
+    m.res_r2 = sys->res_radius * sys->res_radius;
+    m.res_solute_idx = (const int*)(base + lay.res_idx);
+    m.res_solvent_idx = (const int*)(base + lay.res_idx) + shape.n_solute;
+    m.res_state = (unsigned short*)(base + lay.res_state);
+    m.res_n0 = (int*)(base + lay.res_n0);
+    m.res_part = (double*)(base + lay.res_part);
+    m.res_inside = (int*)(base + lay.res_inside);
+    m.res_acf = (double*)(base + lay.res_acf);
+    m.res_cnt = (double*)(base + lay.res_cnt);
+    MS2_HIP(hipMemcpyAsync(base + lay.res_idx, res_idx.data(), res_idx.size() * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+  }
 
   SlotDev* ds = (SlotDev*)b->d_slots.p;
   MDDev* dm = (MDDev*)b->d_md.p;
@@ -519,6 +577,7 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
     return s;
   }
   MS2_HIP(launch_md_init(ds, dm, ctx->d_tab, slot, st));
+  if (shape.n_solute > 0) MS2_HIP(launch_residence(ds, dm, dp, slot, 1, shape.n_solute, st));
   MS2_HIP(hipStreamSynchronize(st));
   h.used = true;
   b->used_bytes += lay.total;
@@ -652,6 +711,13 @@ ms2_status ms2_sample(ms2_batch* b, int32_t slot, ms2_samples* out, void* stream
   if (nl && out->h_acf_j) MS2_HIP(hipMemcpyAsync(out->h_acf_j, h.md.acf_j, nl, hipMemcpyDeviceToHost, st));
   if (nl && out->h_acf_cnt)
     MS2_HIP(hipMemcpyAsync(out->h_acf_cnt, h.md.acf_cnt, nl, hipMemcpyDeviceToHost, st));
+  if (h.shape.n_solute > 0) {
+    if (out->h_res_acf) MS2_HIP(hipMemcpyAsync(out->h_res_acf, h.md.res_acf, nl, hipMemcpyDeviceToHost, st));
+    if (out->h_res_cnt) MS2_HIP(hipMemcpyAsync(out->h_res_cnt, h.md.res_cnt, nl, hipMemcpyDeviceToHost, st));
+  } else {
+    if (out->h_res_acf) std::memset(out->h_res_acf, 0, nl);
+    if (out->h_res_cnt) std::memset(out->h_res_cnt, 0, nl);
+  }
   if (out->h_com) MS2_HIP(hipMemcpyAsync(out->h_com, h.md.r, 3 * n * 8, hipMemcpyDeviceToHost, st));
   if (out->h_quat) MS2_HIP(hipMemcpyAsync(out->h_quat, h.md.q, 4 * n * 8, hipMemcpyDeviceToHost, st));
   if (out->h_vel) MS2_HIP(hipMemcpyAsync(out->h_vel, h.md.vel, 3 * n * 8, hipMemcpyDeviceToHost, st));
@@ -668,6 +734,8 @@ ms2_status ms2_sample(ms2_batch* b, int32_t slot, ms2_samples* out, void* stream
   out->ekin_rot = m.ekin_rot;
   out->pairs_total = m.pairs_total;
   out->site_pairs_total = m.site_pairs_total;
+  out->solvation_sum = m.res_solv_sum;
+  out->solvation_cnt = m.res_solv_cnt;
   return MS2_OK;
 }
 

@@ -149,7 +149,25 @@ struct MDDev {
   double* origin_v;      // [acf_max_live][3][n]
   double* origin_j;      // [acf_max_live][3]
   long long* origin_t0;  // [acf_max_live]
+  // residence time and solvation number, on the ACF schedule
+  int res_on, res_tol, n_solute, n_solvent;
+  int res_due, pad2;     // res_due: a residence sample is pending for step res_step
+  long long res_step;
+  double res_r2;
+  double res_solv_sum, res_solv_cnt;
+  const int* res_solute_idx;   // [n_solute] molecule indices
+  const int* res_solvent_idx;  // [n_solvent]
+  unsigned short* res_state;   // [acf_max_live][n_solute][n_solvent]
+  int* res_n0;                 // [acf_max_live][n_solute] shell population at the origin
+  double* res_part;            // [n_solute][acf_max_live] per-solute fraction (staging)
+  int* res_inside;             // [n_solute] shell population now (staging)
+  double* res_acf;             // [acf_nlag]
+  double* res_cnt;             // [acf_nlag]
 };
+
+// residence state word: the pair no longer counts for this origin
+constexpr unsigned short kResDead = 0xFFFF;
+constexpr int kResMaxLive = 64;    // live ACF origins supported with residence sampling
 
 
 }  // namespace ms2

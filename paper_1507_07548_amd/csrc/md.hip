@@ -15,6 +15,8 @@
 //                      step (Sec. 4; Sec. 5, Eqs. 3-4)
 //   rdf_kernel         site-site radial distribution histogram between LJ
 //                      sites (Sec. 5, Eq. 2), FP64 distances, integer counts
+//   residence_kernel   residence-time correlation and solvation number
+//                      (Sec. 5, Eqs. 7-8) on the extended time step
 // The O(N) kernels use one 1024-thread block per slot so that every
 // reduction (kinetic energy, ACF dot products) is a fixed in-block tree.
 #include <hip/hip_runtime.h>
@@ -203,6 +205,10 @@ __global__ __launch_bounds__(kMdThreads) void md_init_kernel(SlotDev* slots, MDD
     m.ekin_rot = 0.5 * kr2;
   }
   if (m.acf_every > 0) acf_sample(m, tab, sd, vnow, np, 0, red);
+  if (tid == 0 && m.res_on) {
+    m.res_due = 1;
+    m.res_step = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -267,7 +273,12 @@ __global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDe
   __shared__ double red[kMdThreads];
   SlotDev& sd = slots[blockIdx.x];
   MDDev& m = md[blockIdx.x];
-  if (!m.active) return;
+  if (!m.active) {
+    // a finished slot samples nothing more (its last RDF sample was taken
+    // right after the step that ended it)
+    if (threadIdx.x == 0) m.rdf_due = 0;
+    return;
+  }
   const SysParams& P = prm[blockIdx.x];
   const int tid = threadIdx.x, n = sd.n, np = sd.com_ld, ld = sd.com_ld;
   const double dt = m.dt;
@@ -366,7 +377,13 @@ __global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDe
     m.rdf_due = (m.rdf_every > 0 && s % m.rdf_every == 0) ? 1 : 0;
     if (!ok) m.status = MS2_ENONFINITE;
   }
-  if (m.acf_every > 0 && s % m.acf_every == 0) acf_sample(m, tab, sd, v, np, s, red);
+  if (m.acf_every > 0 && s % m.acf_every == 0) {
+    acf_sample(m, tab, sd, v, np, s, red);
+    if (tid == 0 && m.res_on) {
+      m.res_due = 1;
+      m.res_step = s;
+    }
+  }
   __syncthreads();
   if (tid == 0) {
     m.steps_done = s;
@@ -490,6 +507,156 @@ __global__ __launch_bounds__(64 * W) void rdf_kernel(const WorkItem* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Residence time and solvation number (Sec. 5, Eqs. 7-8), sampled with the
+// ACFs.  residence_kernel: one block per (solute, slot).  A solvent molecule
+// is inside the shell when the centres are closer than the radius (FP64,
+// minimum image, no contraction).  Per live origin o, the state word of the
+// pair (solute, solvent) is kResDead (outside the shell at t0, or outside for
+// more than res_tol consecutive samples since: it never counts again for o)
+// or the number of consecutive samples spent outside; the pair counts at a
+// lag while not dead and inside (the tolerance of Impey et al.).  Counts are
+// wave ballots added per wave and then in wave order.  The solute's fraction
+// of its initial shell still resident, per origin, and its shell population
+// now go to staging arrays; residence_reduce_kernel adds them up over the
+// solutes in a fixed order and clears the pending flag.
+// ---------------------------------------------------------------------------
+constexpr int kResThreads = 256;
+
+__global__ __launch_bounds__(kResThreads) void residence_kernel(const SlotDev* __restrict__ slots, MDDev* md,
+                                                                const SysParams* __restrict__ prm,
+                                                                int slot_base) {
+  constexpr int NW = kResThreads / 64;
+  __shared__ int s_lag[kResMaxLive];
+  __shared__ int s_cnt[NW][kResMaxLive];
+  __shared__ int s_in[NW];
+  const int slot = slot_base + blockIdx.y;
+  const MDDev& m = md[slot];
+  if (!m.res_due || (int)blockIdx.x >= m.n_solute) return;
+  const SlotDev& sd = slots[slot];
+  const SysParams& P = prm[slot];
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int live = m.n_origins < m.acf_max_live ? m.n_origins : m.acf_max_live;
+  const long long step = m.res_step;
+  for (int o = tid; o < kResMaxLive; o += kResThreads) {
+    int lag = -1;
+    if (o < live && step >= m.origin_t0[o]) {
+      const long long l = (step - m.origin_t0[o]) / m.acf_every;
+      if (l < m.acf_nlag) lag = (int)l;
+    }
+    s_lag[o] = lag;
+    for (int w = 0; w < NW; ++w) s_cnt[w][o] = 0;
+  }
+  if (tid < NW) s_in[tid] = 0;
+  __syncthreads();
+  const int a = blockIdx.x, ns = m.n_solvent, nu = m.n_solute, ld = sd.com_ld;
+  const int ia = m.res_solute_idx[a];
+  const double xa = sd.com[ia], ya = sd.com[ld + ia], za = sd.com[2 * ld + ia];
+  for (int b0 = wv * 64; b0 < ns; b0 += kResThreads) {
+    const int b = b0 + lane;
+    bool in = false;
+    if (b < ns) {
+      const int ib = m.res_solvent_idx[b];
+      double r2;
+      {
+#pragma clang fp contract(off)
+        double dx = xa - sd.com[ib], dy = ya - sd.com[ld + ib], dz = za - sd.com[2 * ld + ib];
+        dx = dx - P.L * rint(dx * P.invL);
+        dy = dy - P.L * rint(dy * P.invL);
+        dz = dz - P.L * rint(dz * P.invL);
+        r2 = dx * dx + dy * dy + dz * dz;
+      }
+      in = ib != ia && r2 < m.res_r2;
+    }
+    const unsigned long long win = __builtin_amdgcn_ballot_w64(in);
+    if (lane == 0) s_in[wv] += __popcll(win);
+    for (int o = 0; o < live; ++o) {
+      const int lag = s_lag[o];
+      if (lag < 0) continue;
+      bool counts = false;
+      if (b < ns) {
+        unsigned short* stp = m.res_state + ((size_t)o * nu + a) * ns + b;
+        unsigned short v = *stp;
+        if (lag == 0) {
+          v = in ? 0 : kResDead;
+        } else if (v != kResDead) {
+          v = in ? 0 : (unsigned short)(v + 1);
+          if (v != kResDead && (int)v > m.res_tol) v = kResDead;
+        }
+        *stp = v;
+        counts = in && v != kResDead;
+      }
+      const unsigned long long wc = __builtin_amdgcn_ballot_w64(counts);
+      if (lane == 0) s_cnt[wv][o] += __popcll(wc);
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < m.acf_max_live; o += kResThreads) {
+    double frac = -1.0;
+    if (o < live && s_lag[o] >= 0) {
+      int c = 0;
+      for (int w = 0; w < NW; ++w) c += s_cnt[w][o];
+      int* n0p = m.res_n0 + (size_t)o * nu + a;
+      if (s_lag[o] == 0) *n0p = c;      // at the origin every molecule inside counts
+      const int n0 = s_lag[o] == 0 ? c : *n0p;
+      if (n0 > 0) frac = (double)c / (double)n0;
+    }
+    m.res_part[(size_t)a * m.acf_max_live + o] = frac;
+  }
+  if (tid == 0) {
+    int t = 0;
+    for (int w = 0; w < NW; ++w) t += s_in[w];
+    m.res_inside[a] = t;
+  }
+}
+
+__global__ __launch_bounds__(64) void residence_reduce_kernel(MDDev* md, int slot_base) {
+  MDDev& m = md[slot_base + blockIdx.x];
+  if (!m.res_due) return;
+  const int lane = threadIdx.x, nu = m.n_solute, ml = m.acf_max_live;
+  const int live = m.n_origins < ml ? m.n_origins : ml;
+  const long long step = m.res_step;
+  for (int o = 0; o < live; ++o) {
+    if (step < m.origin_t0[o]) continue;
+    const long long lag = (step - m.origin_t0[o]) / m.acf_every;
+    if (lag >= m.acf_nlag) continue;
+    double sum = 0.0;
+    int cnt = 0;
+    for (int a = lane; a < nu; a += 64) {
+      const double f = m.res_part[(size_t)a * ml + o];
+      if (f >= 0.0) {
+        sum += f;
+        cnt += 1;
+      }
+    }
+    for (int h = 32; h > 0; h >>= 1) {
+      sum += __shfl_xor(sum, h, 64);
+      cnt += __shfl_xor(cnt, h, 64);
+    }
+    if (lane == 0) {
+      m.res_acf[lag] += sum;
+      m.res_cnt[lag] += (double)cnt;
+    }
+  }
+  int inside = 0;
+  for (int a = lane; a < nu; a += 64) inside += m.res_inside[a];
+  for (int h = 32; h > 0; h >>= 1) inside += __shfl_xor(inside, h, 64);
+  if (lane == 0) {
+    m.res_solv_sum += (double)inside;
+    m.res_solv_cnt += (double)nu;
+    m.res_due = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_residence(const SlotDev* slots, MDDev* md, const SysParams* prm, int slot_base,
+                            int nslots, int max_solute, hipStream_t st) {
+  if (nslots <= 0 || max_solute <= 0) return hipSuccess;
+  hipLaunchKernelGGL(residence_kernel, dim3(max_solute, nslots), dim3(kResThreads), 0, st, slots, md, prm,
+                     slot_base);
+  hipLaunchKernelGGL(residence_reduce_kernel, dim3(nslots), dim3(64), 0, st, md, slot_base);
+  return hipGetLastError();
+}
+
 hipError_t launch_md_wrap(MDDev* md, const SysParams* prm, int slot, int n, hipStream_t st) {
   hipLaunchKernelGGL(md_wrap_kernel, dim3((n + 255) / 256), dim3(256), 0, st, md, prm, slot, n);
   return hipGetLastError();

@@ -76,6 +76,11 @@ class MDSettings:
     acf_origin_every: int = 0
     acf_nlag: int = 0
     u0: float = 0.0
+    # residence time / solvation number (Sec. 5, Eqs. 7-8), on the ACF schedule
+    res_solute: int = -1            # species of the central molecules, -1 = off
+    res_solvent: int = -1           # species counted around them
+    res_radius: float = 0.0         # shell radius between molecule centres
+    res_tolerance: int = 0          # samples a molecule may spend outside and still count
 
 
 @dataclasses.dataclass

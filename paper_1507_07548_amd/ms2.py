@@ -53,15 +53,19 @@ class System(ctypes.Structure):
                 ("dt", c_double), ("temperature", c_double), ("sample_every", c_int32),
                 ("rdf_every", c_int32), ("rdf_bins", c_int32), ("acf_every", c_int32),
                 ("acf_origin_every", c_int32), ("acf_nlag", c_int32), ("rdf_rmax", c_double),
-                ("u0", c_double), ("h_species", P(c_int32)), ("h_com", P(c_double)),
+                ("u0", c_double), ("res_enable", c_int32), ("res_solute", c_int32),
+                ("res_solvent", c_int32), ("res_tolerance", c_int32), ("res_radius", c_double),
+                ("h_species", P(c_int32)), ("h_com", P(c_double)),
                 ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double))]
 
 
 class Samples(ctypes.Structure):
     _fields_ = [("steps_done", c_int64), ("status", c_int32), ("rdf_ntypes", c_int32),
                 ("sums", c_double * NSUM), ("ekin_trans", c_double), ("ekin_rot", c_double),
-                ("pairs_total", c_double), ("site_pairs_total", c_double), ("moments", c_double * 11), ("h_rdf", P(c_double)), ("h_acf_v", P(c_double)),
-                ("h_acf_j", P(c_double)), ("h_acf_cnt", P(c_double)), ("h_com", P(c_double)),
+                ("pairs_total", c_double), ("site_pairs_total", c_double), ("moments", c_double * 11),
+                ("solvation_sum", c_double), ("solvation_cnt", c_double), ("h_rdf", P(c_double)),
+                ("h_acf_v", P(c_double)), ("h_acf_j", P(c_double)), ("h_acf_cnt", P(c_double)),
+                ("h_res_acf", P(c_double)), ("h_res_cnt", P(c_double)), ("h_com", P(c_double)),
                 ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double)),
                 ("h_force", P(c_double)), ("h_torque", P(c_double))]
 
@@ -250,7 +254,10 @@ def system_struct(system, precision: int, n_steps: Optional[int] = None):
                n_steps=md.n_steps if n_steps is None else n_steps, dt=md.dt, temperature=md.temperature,
                sample_every=md.sample_every, rdf_every=md.rdf_every, rdf_bins=md.rdf_bins,
                acf_every=md.acf_every, acf_origin_every=md.acf_origin_every, acf_nlag=md.acf_nlag,
-               rdf_rmax=md.rdf_rmax, u0=md.u0, h_species=sp.ctypes.data_as(P(c_int32)), h_com=dp(com),
+               rdf_rmax=md.rdf_rmax, u0=md.u0, res_enable=1 if md.res_solute >= 0 else 0,
+               res_solute=max(md.res_solute, 0), res_solvent=max(md.res_solvent, 0),
+               res_radius=md.res_radius, res_tolerance=md.res_tolerance,
+               h_species=sp.ctypes.data_as(P(c_int32)), h_com=dp(com),
                h_quat=dp(quat), h_vel=dp(vel), h_omega=dp(om))
     return s, keep
 
@@ -330,6 +337,8 @@ class Batch:
             buf("acf_v", nlag)
             buf("acf_j", nlag)
             buf("acf_cnt", nlag)
+            buf("res_acf", nlag)
+            buf("res_cnt", nlag)
         if state:
             buf("com", (3, n))
             buf("quat", (4, n))
@@ -340,7 +349,8 @@ class Batch:
         check(lib().ms2_sample(self.handle, slot, ctypes.byref(out), _stream_ptr(stream)))
         res = {"steps_done": out.steps_done, "status": out.status, "sums": np.array(out.sums[:]),
                "ekin_trans": out.ekin_trans, "ekin_rot": out.ekin_rot, "moments": np.array(out.moments[:]),
-               "pairs_total": out.pairs_total, "site_pairs_total": out.site_pairs_total}
+               "pairs_total": out.pairs_total, "site_pairs_total": out.site_pairs_total,
+               "solvation_sum": out.solvation_sum, "solvation_cnt": out.solvation_cnt}
         for k, v in arrays.items():
             res[k] = v.T.copy() if k in ("com", "quat", "vel", "omega", "force", "torque") else v
         return res
