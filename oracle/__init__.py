@@ -47,7 +47,8 @@ class OrMD(ctypes.Structure):
                 ("rdf_bins", c_int32), ("acf_every", c_int32), ("acf_origin_every", c_int32),
                 ("acf_nlag", c_int32), ("rdf_rmax", c_double), ("u0", c_double),
                 ("res_solute", c_int32), ("res_solvent", c_int32), ("res_radius", c_double),
-                ("res_tolerance", c_int32), ("res_pad", c_int32)]
+                ("res_tolerance", c_int32), ("heat_flux", c_int32),
+                ("h_partial", ctypes.POINTER(c_double))]
 
 
 def build(force: bool = False) -> str:
@@ -72,7 +73,8 @@ def lib():
         _lib.or_forces.argtypes = [P(OrSpecies), c_int32, P(OrParams), c_int32, ip, dp, dp, dp, dp, dp]
         _lib.or_kspace.argtypes = _lib.or_forces.argtypes
         _lib.or_md.argtypes = [P(OrSpecies), c_int32, P(OrParams), P(OrMD), c_int32, ip,
-                               dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+                               dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        _lib.or_heat_flux.argtypes = [P(OrSpecies), c_int32, P(OrParams), c_int32, ip, dp, dp, dp, dp, dp, dp]
         _lib.or_rdf_ntypes.argtypes = [P(OrSpecies), c_int32]
         _lib.or_check.argtypes = [P(OrSpecies), c_int32, P(OrParams)]
     return _lib
@@ -187,20 +189,42 @@ def md(system, md_settings=None, want_log: bool = True):
     nlag = max(m.acf_nlag, 1)
     acf_v, acf_j, acf_c = np.zeros(nlag), np.zeros(nlag), np.zeros(nlag)
     res_acf, res_cnt, solv = np.zeros(nlag), np.zeros(nlag), np.zeros(2)
+    acf_q, acf_q_cnt = np.zeros(nlag), np.zeros(nlag)
+    hp = np.zeros(len(st.species))
+    if getattr(m, "h_partial", None) is not None:
+        hp[:] = np.asarray(m.h_partial, dtype=np.float64)
     cfg = OrMD(integrator=m.integrator, n_steps=m.n_steps, dt=m.dt, temperature=m.temperature,
                sample_every=m.sample_every, rdf_every=m.rdf_every, rdf_bins=m.rdf_bins,
                acf_every=m.acf_every, acf_origin_every=m.acf_origin_every, acf_nlag=m.acf_nlag,
                rdf_rmax=m.rdf_rmax, u0=m.u0, res_solute=getattr(m, "res_solute", -1),
                res_solvent=getattr(m, "res_solvent", -1), res_radius=getattr(m, "res_radius", 0.0),
-               res_tolerance=getattr(m, "res_tolerance", 0))
+               res_tolerance=getattr(m, "res_tolerance", 0), heat_flux=1 if getattr(m, "heat_flux", False) else 0,
+               h_partial=_dp(hp))
     sp, p = species_array(st.species), params_struct(st.params)
     rc = lib().or_md(sp, len(st.species), ctypes.byref(p), ctypes.byref(cfg), n,
                      idx.ctypes.data_as(ctypes.POINTER(c_int32)), _dp(com), _dp(quat), _dp(vel),
                      _dp(omega), _dp(log), _dp(moments), _dp(rdf), _dp(acf_v), _dp(acf_j), _dp(acf_c),
-                     _dp(res_acf), _dp(res_cnt), _dp(solv))
+                     _dp(res_acf), _dp(res_cnt), _dp(solv), _dp(acf_q), _dp(acf_q_cnt))
     if rc:
         raise ValueError(f"or_md rejected its arguments ({rc})")
     st.com, st.quat, st.vel, st.omega = com, quat, vel, omega
     return {"state": st, "log": log, "moments": moments, "rdf": rdf,
             "acf_v": acf_v, "acf_j": acf_j, "acf_cnt": acf_c, "res_acf": res_acf, "res_cnt": res_cnt,
-            "solvation_sum": solv[0], "solvation_cnt": solv[1]}
+            "solvation_sum": solv[0], "solvation_cnt": solv[1], "acf_q": acf_q, "acf_q_cnt": acf_q_cnt}
+
+
+def heat_flux(system, vel=None, omega=None, h_partial=None) -> np.ndarray:
+    """Heat flux J_q (Sec. 5, Eq. 6) of one state: vel [n,3] lab, omega
+    [n,3] body frame (default: the system's), h_partial per species."""
+    idx, com, quat = _arrays(system)
+    v = np.ascontiguousarray(system.vel if vel is None else vel, dtype=np.float64)
+    w = np.ascontiguousarray(system.omega if omega is None else omega, dtype=np.float64)
+    hp = np.zeros(len(system.species)) if h_partial is None else np.ascontiguousarray(h_partial, dtype=np.float64)
+    jq = np.zeros(3)
+    sp, p = species_array(system.species), params_struct(system.params)
+    rc = lib().or_heat_flux(sp, len(system.species), ctypes.byref(p), idx.shape[0],
+                            idx.ctypes.data_as(ctypes.POINTER(c_int32)), _dp(com), _dp(quat), _dp(v), _dp(w),
+                            _dp(hp), _dp(jq))
+    if rc:
+        raise ValueError(f"or_heat_flux rejected its arguments ({rc})")
+    return jq

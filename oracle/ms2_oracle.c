@@ -423,6 +423,66 @@ int or_forces(const or_species* sp, int32_t nsp, const or_params* p, int32_t n,
 }
 
 /* ------------------------------------------------------------------ */
+/* heat flux (Sec. 5, Eq. 6); the energy moment sum_k R_k e_k with       */
+/* e_k = kinetic energy + half of k's pair energies changes at this rate */
+/* ------------------------------------------------------------------ */
+int or_heat_flux(const or_species* sp, int32_t nsp, const or_params* p, int32_t n,
+                 const int32_t* species, const double* com, const double* quat,
+                 const double* vel, const double* omega, const double* h_partial, double* jq) {
+  int rc_ok = or_check(sp, nsp, p);
+  if (rc_ok) return rc_ok;
+  if (p->elec == OR_ELEC_EWALD) return -40;
+  if (n < 1 || !species || !com || !quat || !vel || !omega || !jq) return -10;
+  double L = p->box, rc2 = p->rc * p->rc;
+  rf_t rf = {0.0, 0.0};
+  if (p->elec == OR_ELEC_RF) {
+    rf.k_rf = isinf(p->eps_rf) ? 1.0 / (2.0 * p->rc * p->rc * p->rc)
+                               : (p->eps_rf - 1.0) / ((2.0 * p->eps_rf + 1.0) * p->rc * p->rc * p->rc);
+    rf.c_rf = 1.0 / p->rc + rf.k_rf * p->rc * p->rc;
+  }
+  lab_t* lab = (lab_t*)malloc(sizeof(lab_t) * (size_t)n);
+  double* wlab = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  if (!lab || !wlab) { free(lab); free(wlab); return -12; }
+  for (int k = 0; k < 3; ++k) jq[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const or_species* s = &sp[species[i]];
+    lab_sites(s, quat + 4 * i, &lab[i]);
+    double A[3][3];
+    quat_matrix(quat + 4 * i, A);
+    mat_vec(A, omega + 3 * i, wlab + 3 * i);
+    double e = 0.5 * s->mass * dot3(vel + 3 * i, vel + 3 * i);
+    for (int k = 0; k < 3; ++k) e += 0.5 * s->inertia[k] * omega[3 * i + k] * omega[3 * i + k];
+    if (h_partial) e -= h_partial[species[i]];
+    for (int k = 0; k < 3; ++k) jq[k] += e * vel[3 * i + k];
+  }
+  for (int i = 0; i < n; ++i) {
+    for (int j = i + 1; j < n; ++j) {
+      double R[3];
+      for (int k = 0; k < 3; ++k) {
+        double d = com[3 * i + k] - com[3 * j + k];
+        R[k] = d - L * rint(d / L);
+      }
+      double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      if (!(r2 < rc2)) continue;
+      pair_acc o;
+      memset(&o, 0, sizeof(o));
+      const or_species* si = &sp[species[i]];
+      const or_species* sj = &sp[species[j]];
+      for (int a = 0; a < si->n_sites; ++a)
+        for (int b = 0; b < sj->n_sites; ++b)
+          site_pair(si, a, sj, b, &lab[i], &lab[j], R, p, &rf, &o);
+      double u = o.u_lj + o.u_el, vs[3];
+      for (int k = 0; k < 3; ++k) vs[k] = vel[3 * i + k] + vel[3 * j + k];
+      double power = dot3(o.f, vs) + dot3(o.ti, wlab + 3 * i) - dot3(o.tj, wlab + 3 * j);
+      for (int k = 0; k < 3; ++k) jq[k] += 0.5 * u * vs[k] + 0.5 * R[k] * power;
+    }
+  }
+  free(lab);
+  free(wlab);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Ewald reciprocal space, explicit loop over the full k sphere (Sec. 4) */
 /* ------------------------------------------------------------------ */
 int or_kspace(const or_species* sp, int32_t nsp, const or_params* p, int32_t n,
@@ -722,6 +782,36 @@ static void residence_sample(res_t* R, int s, const double* com, double L, doubl
   }
 }
 
+/* Heat-flux autocorrelation (Sec. 5, Eq. 5) on the ACF schedule: the flux
+ * is evaluated with each step's force evaluation (Gear: predicted state;
+ * velocity Verlet: after the drift, with the half-step velocities); the
+ * initial state has none, so an origin at step 0 carries no flux. */
+typedef struct {
+  int on, nlag, every, origin_every, max_live, n_origins;
+  int* t0;
+  int* valid;
+  double* j0;   /* [max_live][3] */
+} hf_t;
+
+static void heat_acf_sample(hf_t* H, int s, const double* jq, int have, double* acf_q, double* acf_q_cnt) {
+  if (s % H->origin_every == 0) {
+    int o = H->n_origins % H->max_live;
+    H->t0[o] = s;
+    H->valid[o] = have;
+    for (int k = 0; k < 3; ++k) H->j0[3 * o + k] = have ? jq[k] : 0.0;
+    H->n_origins++;
+  }
+  if (!have) return;
+  int live = H->n_origins < H->max_live ? H->n_origins : H->max_live;
+  for (int o = 0; o < live; ++o) {
+    if (!H->valid[o] || s < H->t0[o]) continue;
+    int lag = (s - H->t0[o]) / H->every;
+    if (lag >= H->nlag) continue;
+    if (acf_q) acf_q[lag] += dot3(H->j0 + 3 * o, jq);
+    if (acf_q_cnt) acf_q_cnt[lag] += 1.0;
+  }
+}
+
 /* RDF histogram between all LJ sites (Sec. 5, Eq. 2): unordered site pairs of
  * distinct molecules, site distance from the minimum-image centre shift;
  * bin = (int)(r * bins / rmax). */
@@ -787,7 +877,8 @@ static void wrap_box(double* x, int n3, double L) {
 int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg* cfg,
           int32_t n, const int32_t* species, double* com, double* quat, double* vel,
           double* omega, double* energy_log, double* moments, double* rdf, double* acf_v,
-          double* acf_j, double* acf_cnt, double* res_acf, double* res_cnt, double* solvation) {
+          double* acf_j, double* acf_cnt, double* res_acf, double* res_cnt, double* solvation,
+          double* acf_q, double* acf_q_cnt) {
   int e = or_check(sp, nsp, p);
   if (e) return e;
   if (!cfg || n < 2 || cfg->n_steps < 0 || !(cfg->dt > 0.0)) return -30;
@@ -817,6 +908,23 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
     acf.t0 = calloc((size_t)acf.max_live, sizeof(int));
     acf.v0 = calloc((size_t)acf.max_live * n3, sizeof(double));
     acf.j0 = calloc((size_t)acf.max_live * 3, sizeof(double));
+  }
+  hf_t hf;
+  memset(&hf, 0, sizeof(hf));
+  double jq[3] = {0.0, 0.0, 0.0};
+  if (cfg->heat_flux) {
+    if (cfg->acf_every <= 0 || p->elec == OR_ELEC_EWALD) {
+      free(F); free(Tq); free(acf.t0); free(acf.v0); free(acf.j0);
+      return -35;
+    }
+    hf.on = 1;
+    hf.nlag = cfg->acf_nlag;
+    hf.every = cfg->acf_every;
+    hf.origin_every = cfg->acf_origin_every;
+    hf.max_live = acf.max_live;
+    hf.t0 = calloc((size_t)hf.max_live, sizeof(int));
+    hf.valid = calloc((size_t)hf.max_live, sizeof(int));
+    hf.j0 = calloc((size_t)hf.max_live * 3, sizeof(double));
   }
   res_t res;
   memset(&res, 0, sizeof(res));
@@ -863,6 +971,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
     }
     if (acf.n) acf_sample(&acf, 0, vel, sp, species, acf_v, acf_j, acf_cnt);
     if (res.on) residence_sample(&res, 0, com, L, res_acf, res_cnt, solvation);
+    if (hf.on) heat_acf_sample(&hf, 0, jq, 0, acf_q, acf_q_cnt);
     for (int s = 1; s <= cfg->n_steps; ++s) {
       for (int i = 0; i < n; ++i) {
         double m = sp[species[i]].mass;
@@ -874,6 +983,10 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
       wrap_box(com, (int)n3, L);
       e = evaluate(sp, nsp, p, n, species, com, quat, F, Tq, sums);
       if (e) goto done;
+      if (hf.on && s % cfg->acf_every == 0) {
+        e = or_heat_flux(sp, nsp, p, n, species, com, quat, vel, omega, cfg->h_partial, jq);
+        if (e) goto done;
+      }
       for (int i = 0; i < n; ++i) {
         double m = sp[species[i]].mass;
         for (int k = 0; k < 3; ++k) vel[3 * i + k] += 0.5 * dt / m * F[3 * i + k];
@@ -896,6 +1009,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
         rdf_sample(sp, nsp, p, cfg, n, species, com, quat, rdf);
       if (acf.n && s % cfg->acf_every == 0) acf_sample(&acf, s, vel, sp, species, acf_v, acf_j, acf_cnt);
       if (res.on && s % cfg->acf_every == 0) residence_sample(&res, s, com, L, res_acf, res_cnt, solvation);
+      if (hf.on && s % cfg->acf_every == 0) heat_acf_sample(&hf, s, jq, 1, acf_q, acf_q_cnt);
     }
     goto done;
   }
@@ -941,6 +1055,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
     }
     if (acf.n) acf_sample(&acf, 0, vel, sp, species, acf_v, acf_j, acf_cnt);
     if (res.on) residence_sample(&res, 0, com, L, res_acf, res_cnt, solvation);
+    if (hf.on) heat_acf_sample(&hf, 0, jq, 0, acf_q, acf_q_cnt);
 
     for (int s = 1; s <= cfg->n_steps && !e; ++s) {
       gear_predict(r, (int)n3);
@@ -955,6 +1070,11 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
       }
       e = evaluate(sp, nsp, p, n, species, r[0], q[0], F, Tq, sums);
       if (e) break;
+      if (hf.on && s % cfg->acf_every == 0) {   /* flux at the predicted state */
+        for (size_t c = 0; c < n3; ++c) vtmp[c] = r[1][c] / dt;
+        e = or_heat_flux(sp, nsp, p, n, species, r[0], q[0], vtmp, w[0], cfg->h_partial, jq);
+        if (e) break;
+      }
       for (int i = 0; i < n; ++i) {
         const or_species* sx = &sp[species[i]];
         for (int k = 0; k < 3; ++k) {
@@ -1016,6 +1136,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
         acf_sample(&acf, s, vtmp, sp, species, acf_v, acf_j, acf_cnt);
       }
       if (res.on && s % cfg->acf_every == 0) residence_sample(&res, s, r[0], L, res_acf, res_cnt, solvation);
+      if (hf.on && s % cfg->acf_every == 0) heat_acf_sample(&hf, s, jq, 1, acf_q, acf_q_cnt);
     }
     memcpy(com, r[0], n3 * sizeof(double));
     memcpy(quat, q[0], n4 * sizeof(double));
@@ -1028,5 +1149,6 @@ done:
   free(F); free(Tq);
   free(acf.t0); free(acf.v0); free(acf.j0);
   free(res.solute); free(res.solvent); free(res.t0); free(res.n0); free(res.away);
+  free(hf.t0); free(hf.valid); free(hf.j0);
   return e;
 }

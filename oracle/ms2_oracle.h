@@ -95,7 +95,9 @@ typedef struct {
   double res_radius;        /* shell radius between molecule centres    */
   int32_t res_tolerance;    /* samples a molecule may stay outside and
                                still count as resident                  */
-  int32_t res_pad;
+  int32_t heat_flux;        /* 1: heat-flux ACF on the ACF schedule     */
+  const double* h_partial;  /* [nsp] partial molar enthalpy per molecule
+                               of each species (NULL = 0)               */
 } or_md_cfg;
 
 /* moments[] slots: sums over samples of powers and products of
@@ -138,7 +140,22 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p,
           double* com, double* quat, double* vel, double* omega,
           double* energy_log, double* moments, double* rdf,
           double* acf_v, double* acf_j, double* acf_cnt,
-          double* res_acf, double* res_cnt, double* solvation);
+          double* res_acf, double* res_cnt, double* solvation,
+          double* acf_q, double* acf_q_cnt);
+
+/* Microscopic heat flux of rigid molecules (Sec. 5, Eq. 6) at one state:
+ *   J_q = sum_k (m_k v_k^2 / 2 + w_k.I_k.w_k / 2 - h_k) v_k
+ *       + sum over pairs k < l inside the cut-off of
+ *         u_kl (v_k + v_l) / 2
+ *         + R_kl (F_kl.(v_k + v_l) + tau_kl.w_k - tau_lk.w_l) / 2
+ * with R_kl = R_k - R_l (minimum image), F_kl the force on k from l,
+ * tau_kl the torque on k from l about its centre, w the lab angular
+ * velocity and h_k the partial enthalpy per molecule of k's species.
+ * vel[n][3] lab frame, omega[n][3] body frame (as in or_md), h_partial[nsp]
+ * or NULL.  Reaction field or no electrostatics only (Ewald: -40). */
+int or_heat_flux(const or_species* sp, int32_t nsp, const or_params* p, int32_t n,
+                 const int32_t* species, const double* com, const double* quat,
+                 const double* vel, const double* omega, const double* h_partial, double* jq);
 
 /* Number of LJ site types (one per LJ site of each species) used by the
  * RDF; histograms are stored for every unordered type pair (t1 <= t2). */

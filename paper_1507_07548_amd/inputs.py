@@ -81,6 +81,9 @@ class MDSettings:
     res_solvent: int = -1           # species counted around them
     res_radius: float = 0.0         # shell radius between molecule centres
     res_tolerance: int = 0          # samples a molecule may spend outside and still count
+    # heat-flux ACF (Sec. 5, Eqs. 5-6), on the ACF schedule
+    heat_flux: bool = False
+    h_partial: Optional[tuple] = None   # partial molar enthalpy per molecule, per species
 
 
 @dataclasses.dataclass
