@@ -174,6 +174,11 @@ typedef struct {
   int32_t res_tolerance;     /* samples a molecule may spend outside the shell
                                 and still count as resident (Impey et al.) */
   double res_radius;         /* shell radius between molecule centres (< box/2) */
+  int32_t heat_flux;         /* 1: heat-flux ACF (Sec. 5, Eqs. 5-6) sampled with
+                                the ACFs; reaction field or no electrostatics */
+  int32_t hf_pad;
+  double h_partial[MS2_MAX_SPECIES]; /* partial molar enthalpy per molecule of
+                                each species (energy units of the potential) */
   const int32_t* h_species;  /* [n]    */
   const double* h_com;       /* [3][n] */
   const double* h_quat;      /* [4][n] */
@@ -253,6 +258,9 @@ typedef struct {
                                 non-empty shell at t0 of the fraction of its
                                 initial shell still resident at lag l      */
   double* h_res_cnt;         /* [acf_nlag] number of those terms per lag   */
+  double* h_acf_q;           /* [acf_nlag] sum over origins of J_q(t0).J_q(t0+l n) */
+  double* h_acf_q_cnt;       /* [acf_nlag] origins per lag (an origin at step 0
+                                carries no flux)                           */
   double* h_com;             /* optional [3][n] current state              */
   double* h_quat;            /* optional [4][n]                            */
   double* h_vel;             /* optional [3][n]                            */
@@ -264,7 +272,13 @@ typedef struct {
 /* Copies a slot's accumulated samples and (optionally) its state to host
  * memory; synchronizes `stream`.  Lustig moments (Sec. 3, Eq. 1), RDF
  * (Sec. 5, Eq. 2), velocity and electric-current ACFs (Sec. 5, Eqs. 3-4),
- * residence-time correlation and solvation-number sums (Sec. 5, Eqs. 7-8).
+ * residence-time correlation and solvation-number sums (Sec. 5, Eqs. 7-8),
+ * heat-flux autocorrelation (Sec. 5, Eqs. 5-6).  The heat flux of rigid
+ * molecules, J_q = sum_k (m v^2/2 + w.I.w/2 - h_k) v_k + sum over pairs of
+ * u (v_k + v_l)/2 + R_kl (F_kl.(v_k + v_l) + tau_kl.w_k - tau_lk.w_l)/2, is
+ * evaluated with each step's force evaluation (Gear: predicted state;
+ * velocity Verlet: half-step velocities); lambda = (1/(3 V k T^2)) x the
+ * integral of h_acf_q / h_acf_q_cnt.
  * Residence: at a time origin t0 every solvent molecule inside the shell of
  * a solute is tracked; it counts at lag l while inside the shell, unless it
  * has been outside for more than res_tolerance consecutive samples since t0

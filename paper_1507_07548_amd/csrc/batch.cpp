@@ -23,7 +23,7 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, const WorkItem* items, int base,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, const WorkItem* items, int base,
                        int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
@@ -61,6 +61,7 @@ struct SlotLayout {
   size_t skp, sk, fk, kred, ksum, moments, rdf, acf_v, acf_j, acf_cnt, origin_v, origin_j,
       origin_t0;
   size_t res_idx, res_state, res_n0, res_part, res_inside, res_acf, res_cnt;
+  size_t hf_kin, hf_jq, acf_q, acf_q_cnt, origin_jq, origin_jq_valid;
   size_t total;
 };
 
@@ -68,6 +69,7 @@ struct SlotShape {
   int n, npad, cls, precision, jsplits, nitems, waves, jchunk, mode, nk, kchunks, mchunks, mtiles;
   int rdf_ntp, rdf_bins, acf_nlag, acf_max_live;
   int n_solute, n_solvent;   // residence sampling (0 = off)
+  int heat_flux;             // heat-flux ACF (symmetric items)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -113,6 +115,13 @@ SlotLayout layout_of(const SlotShape& s) {
   L.res_inside = take(nu * 4);
   L.res_acf = take(s.n_solute ? (size_t)s.acf_nlag * 8 : 0);
   L.res_cnt = take(s.n_solute ? (size_t)s.acf_nlag * 8 : 0);
+  const size_t hf = s.heat_flux ? 1 : 0;
+  L.hf_kin = take(hf * 6 * np * rs);
+  L.hf_jq = take(hf * 3 * 8);
+  L.acf_q = take(hf * (size_t)s.acf_nlag * 8);
+  L.acf_q_cnt = take(hf * (size_t)s.acf_nlag * 8);
+  L.origin_jq = take(hf * (size_t)s.acf_max_live * 3 * 8);
+  L.origin_jq_valid = take(hf * (size_t)s.acf_max_live * 4);
   L.total = off;
   return L;
 }
@@ -152,7 +161,7 @@ struct ms2_batch {
   std::vector<SlotHost> slots;
   DevBuf d_slots, d_md, d_prm, d_items;
   // work items grouped by (precision, waves): [begin, end) into d_items
-  struct Group { int precision, waves, begin, end; };
+  struct Group { int precision, waves, begin, end; bool heat_flux; };
   std::vector<Group> groups;
   bool dirty = true;
   int max_n = 2, max_kblocks = 1, max_mchunks = 1, max_mtiles = 1, max_kchunks = 1;
@@ -210,7 +219,11 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
   s.cls = ctx->cls;
   s.precision = sys->params.precision;
   s.mode = mode;
-  const TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
+  TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
+  if (sys->heat_flux) {    // the heat-flux pair part is evaluated on symmetric items only
+    cfg.waves = 0;
+    cfg.jchunk = 64;
+  }
   s.waves = cfg.waves;
   s.jchunk = cfg.jchunk;   // frozen at admission: the slot's buffers are sized for it
   if (cfg.waves == 0) {    // symmetric tile pairs
@@ -243,6 +256,12 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
     s.acf_nlag = sys->acf_nlag;
     s.acf_max_live = (int)((long long)sys->acf_nlag * sys->acf_every / sys->acf_origin_every + 2);
   }
+  if (sys->heat_flux) {
+    if (sys->acf_every <= 0) return set_error(MS2_EINVAL, "the heat flux is sampled with the ACFs: acf_every > 0");
+    if (sys->params.elec == MS2_ELEC_EWALD)
+      return set_error(MS2_EINVAL, "heat flux with Ewald summation is not supported");
+    s.heat_flux = 1;
+  }
   if (sys->res_enable) {
     if (sys->acf_every <= 0) return set_error(MS2_EINVAL, "residence sampling runs on the ACF schedule: acf_every > 0");
     if (sys->res_solute < 0 || sys->res_solute >= ctx->tab.nsp || sys->res_solvent < 0 ||
@@ -271,11 +290,12 @@ void rebuild_items(ms2_batch* b) {
   b->any_ewald = b->any_rdf = b->any_res = false;
   b->max_solute = 0;
   for (int prec : {MS2_FP64, MS2_FP32})
+    for (int hfv : {0, 1})
     for (int waves : {0, 1, 4}) {
-      ms2_batch::Group g{prec, waves, (int)all.size(), 0};
+      ms2_batch::Group g{prec, waves, (int)all.size(), 0, hfv == 1};
       for (int s = 0; s < b->max_slots; ++s) {
         const SlotHost& h = b->slots[s];
-        if (!h.used || h.shape.precision != prec || h.shape.waves != waves) continue;
+        if (!h.used || h.shape.precision != prec || h.shape.waves != waves || h.shape.heat_flux != hfv) continue;
         TileCfg c;
         c.waves = h.shape.waves;
         c.jchunk = h.shape.jchunk;
@@ -322,7 +342,7 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
   }
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_begin[timed_step], st));
   for (auto& g : b->groups)
-    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, di, g.begin, g.end - g.begin, ds, dp, ctx->d_tab,
+    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, di, g.begin, g.end - g.begin, ds, dp, ctx->d_tab,
                         st));
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
   MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
@@ -477,6 +497,22 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   d.sites = base + lay.sites;
   d.pf = base + lay.pf;
   d.pf_single = shape.precision == MS2_FP32 ? 1 : 0;
+  if (shape.heat_flux) {
+    // velocities as held during the force evaluation: Gear r1 = dt v
+    // (predicted), or the velocity-Verlet half-step velocities
+    d.heat_flux = 1;
+    d.hf_kin = base + lay.hf_kin;
+    d.jq = (double*)(base + lay.hf_jq);
+    if (sys->integrator == MS2_GEAR) {
+      d.hf_v = (const double*)(base + lay.r) + 3 * (size_t)n;
+      d.hf_vscale = 1.0 / sys->dt;
+      d.hf_w = (const double*)(base + lay.w);
+    } else {
+      d.hf_v = (const double*)(base + lay.vel);
+      d.hf_vscale = 1.0;
+      d.hf_w = nullptr;
+    }
+  }
   d.bsum = (double*)(base + lay.bsum);
   d.force = (double*)(base + lay.force);
   d.torque = (double*)(base + lay.torque);
@@ -537,6 +573,14 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   m.origin_v = (double*)(base + lay.origin_v);
   m.origin_j = (double*)(base + lay.origin_j);
   m.origin_t0 = (long long*)(base + lay.origin_t0);
+  if (shape.heat_flux) {
+    m.hf_on = 1;
+    for (int a = 0; a < kMaxSp; ++a) m.h_partial[a] = sys->h_partial[a];
+    m.acf_q = (double*)(base + lay.acf_q);
+    m.acf_q_cnt = (double*)(base + lay.acf_q_cnt);
+    m.origin_jq = (double*)(base + lay.origin_jq);
+    m.origin_jq_valid = (int*)(base + lay.origin_jq_valid);
+  }
   std::vector<int> res_idx;
   if (shape.n_solute > 0) {
     for (int i = 0; i < n; ++i)
@@ -711,6 +755,14 @@ ms2_status ms2_sample(ms2_batch* b, int32_t slot, ms2_samples* out, void* stream
   if (nl && out->h_acf_j) MS2_HIP(hipMemcpyAsync(out->h_acf_j, h.md.acf_j, nl, hipMemcpyDeviceToHost, st));
   if (nl && out->h_acf_cnt)
     MS2_HIP(hipMemcpyAsync(out->h_acf_cnt, h.md.acf_cnt, nl, hipMemcpyDeviceToHost, st));
+  if (h.shape.heat_flux) {
+    if (out->h_acf_q) MS2_HIP(hipMemcpyAsync(out->h_acf_q, h.md.acf_q, nl, hipMemcpyDeviceToHost, st));
+    if (out->h_acf_q_cnt)
+      MS2_HIP(hipMemcpyAsync(out->h_acf_q_cnt, h.md.acf_q_cnt, nl, hipMemcpyDeviceToHost, st));
+  } else {
+    if (out->h_acf_q) std::memset(out->h_acf_q, 0, nl);
+    if (out->h_acf_q_cnt) std::memset(out->h_acf_q_cnt, 0, nl);
+  }
   if (h.shape.n_solute > 0) {
     if (out->h_res_acf) MS2_HIP(hipMemcpyAsync(out->h_res_acf, h.md.res_acf, nl, hipMemcpyDeviceToHost, st));
     if (out->h_res_cnt) MS2_HIP(hipMemcpyAsync(out->h_res_cnt, h.md.res_cnt, nl, hipMemcpyDeviceToHost, st));

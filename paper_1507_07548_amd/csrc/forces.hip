@@ -81,6 +81,18 @@ __global__ __launch_bounds__(256) void site_frame_kernel(const SlotDev* __restri
     put(D.qd_pos[a < D.nqd ? a : 0], a < D.nqd);
     put(D.qd_axis[a < D.nqd ? a : 0], a < D.nqd);
   }
+  if (sd.hf_kin) {
+    // lab-frame velocity and angular velocity of the state the forces are
+    // evaluated at (heat flux)
+    Real* kin = reinterpret_cast<Real*>(sd.hf_kin);
+    double wb[3] = {0.0, 0.0, 0.0};
+    if (sd.hf_w)
+      for (int c = 0; c < 3; ++c) wb[c] = sd.hf_w[c * ld + i];
+    for (int c = 0; c < 3; ++c) {
+      kin[c * np + i] = (Real)(sd.hf_v[c * ld + i] * sd.hf_vscale);
+      kin[(3 + c) * np + i] = (Real)(A[c][0] * wb[0] + A[c][1] * wb[1] + A[c][2] * wb[2]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -242,7 +254,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
     pf[0 * np + i] = (Real)F[0]; pf[1 * np + i] = (Real)F[1]; pf[2 * np + i] = (Real)F[2];
     pf[3 * np + i] = (Real)T[0]; pf[4 * np + i] = (Real)T[1]; pf[5 * np + i] = (Real)T[2];
   }
-  double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
+  double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns, 0.0, 0.0, 0.0};
   if constexpr (W > 1)
     block_sums<TJ>(s_red, v, sd.bsum + (size_t)it.local * kNumBlockSums);
   else
@@ -306,11 +318,12 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <typename Real, int NR>
+template <typename Real, int NR, bool HF>
 struct SymTiles {
   double com[2][3][64];                 // [rows, columns][xyz][molecule]
   Real site[2][NR][64];
   Real stage[kSymWaves][9][64];         // F_i, tau_i, tau_j of each lane's pair
+  Real kin[HF ? 2 : 1][6][HF ? 64 : 1]; // heat flux: lab v and w of rows, columns
 };
 
 template <typename Real>
@@ -319,7 +332,7 @@ struct SymFinal {
   double sums[kSymWaves][kNumBlockSums];
 };
 
-template <typename Real, int C>
+template <typename Real, int C, bool HF>
 __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   int item_base,
                                                                   const SlotDev* __restrict__ slots,
@@ -329,7 +342,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
   constexpr int TJ = 64, NW = kSymWaves;
 
   __shared__ union {
-    SymTiles<Real, NR> t;
+    SymTiles<Real, NR, HF> t;
     SymFinal<Real> f;
   } u;
   __shared__ int s_sp[2][TJ];
@@ -375,6 +388,16 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
       for (int k = 0; k < NR; ++k) r[k] = gsite[k * np + mc];
 #pragma unroll
       for (int k = 0; k < NR; ++k) u.t.site[side][k][lane] = r[k];
+    }
+    if constexpr (HF) {
+      if (wv < 2) {
+        const Real* kin = reinterpret_cast<const Real*>(sd.hf_kin);
+        Real kv[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) kv[c] = kin[c * np + mc];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) u.t.kin[side][c][lane] = kv[c];
+      }
     }
     s_list[wv][lane] = 0;
   }
@@ -422,6 +445,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
 
   // 2.-3. the diagonal-major list, one pair per lane, chunks dealt to waves
   double a_ulj = 0, a_uel = 0, a_us = 0, a_uss = 0;
+  double a_jq[3] = {0, 0, 0};
   int a_np = 0, a_ns = 0;
   Real g_row[6] = {0, 0, 0, 0, 0, 0}, g_col[6] = {0, 0, 0, 0, 0, 0};
   Real(*stage)[TJ] = u.t.stage[wv];
@@ -460,6 +484,8 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
                                            ai, unused, acc);
     Real Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0};
     fold_sites<Real, C, 1, Real>(rec, ai, Fi, Ti);
+    const Real Tj[3] = {-Ti[0] - (Ry * Fi[2] - Rz * Fi[1]), -Ti[1] - (Rz * Fi[0] - Rx * Fi[2]),
+                        -Ti[2] - (Rx * Fi[1] - Ry * Fi[0])};
     if (valid) {
       a_ulj += (double)acc.ulj;
       a_uel += (double)acc.uel;
@@ -467,6 +493,20 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
       a_us -= (double)(Rx * acc.fx + Ry * acc.fy + Rz * acc.fz);
       a_np += 1;
       a_ns += s_tab.nsite[spi][spj];
+      if constexpr (HF) {
+        // pair part of the heat flux: u (v_i + v_j)/2 + R (F.(v_i + v_j) +
+        // tau_i.w_i - tau_j.w_j)/2
+        Real vs[3], pw = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          vs[c] = u.t.kin[0][c][row] + u.t.kin[1][c][col];
+          pw += Fi[c] * vs[c] + Ti[c] * u.t.kin[0][3 + c][row] - Tj[c] * u.t.kin[1][3 + c][col];
+        }
+        const Real up = acc.ulj + acc.uel;
+        a_jq[0] += 0.5 * ((double)(up * vs[0]) + (double)(Rx * pw));
+        a_jq[1] += 0.5 * ((double)(up * vs[1]) + (double)(Ry * pw));
+        a_jq[2] += 0.5 * ((double)(up * vs[2]) + (double)(Rz * pw));
+      }
     }
     stage[0][lane] = Fi[0];
     stage[1][lane] = Fi[1];
@@ -474,9 +514,9 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     stage[3][lane] = Ti[0];
     stage[4][lane] = Ti[1];
     stage[5][lane] = Ti[2];
-    stage[6][lane] = -Ti[0] - (Ry * Fi[2] - Rz * Fi[1]);
-    stage[7][lane] = -Ti[1] - (Rz * Fi[0] - Rx * Fi[2]);
-    stage[8][lane] = -Ti[2] - (Rx * Fi[1] - Ry * Fi[0]);
+    stage[6][lane] = Tj[0];
+    stage[7][lane] = Tj[1];
+    stage[8][lane] = Tj[2];
     wave_sync_lds();
     // gather: molecule `lane` of tile I at its own entry index; molecule
     // `lane` of tile J is the column of row lane - dd
@@ -499,7 +539,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
   }
 
   // 5. the waves' partials, added in wave order
-  double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns};
+  double v[kNumBlockSums] = {a_ulj, a_uel, a_us, a_uss, (double)a_np, (double)a_ns, a_jq[0], a_jq[1], a_jq[2]};
   __syncthreads();                           // tiles and stages are dead from here
   wave_sums(v, u.f.sums[wv]);
 #pragma unroll
@@ -594,7 +634,7 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
   }
   const int ni = sd.nitems;
   const int per = (ni + 255) / 256;
-  double acc[kNumBlockSums] = {0, 0, 0, 0, 0, 0};
+  double acc[kNumBlockSums] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = tid * per; t < min(ni, (tid + 1) * per); ++t)
 #pragma unroll
     for (int k = 0; k < kNumBlockSums; ++k) acc[k] += sd.bsum[(size_t)t * kNumBlockSums + k];
@@ -622,6 +662,8 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
     out[MS2_SUM_NPAIR] = h * s_red[4][0];
     out[MS2_SUM_NSITE] = h * s_red[5][0];
     out[MS2_SUM_U_RECIP] = 0.0;
+    if (sd.jq)
+      for (int c = 0; c < 3; ++c) sd.jq[c] = s_red[6 + c][0];
     double uc = 0.0, ul = 0.0, usl = 0.0, ussl = 0.0;
     for (int a = 0; a < P.nsp; ++a) {
       const double na = (double)s_cnt[a][0];
@@ -680,29 +722,34 @@ static hipError_t launch_pair_cw(const WorkItem* items, int base, int count, con
 }
 
 template <typename Real, int C>
-static hipError_t launch_pair_c(int waves, const WorkItem* items, int base, int count,
+static hipError_t launch_pair_c(int waves, bool heat_flux, const WorkItem* items, int base, int count,
                                 const SlotDev* slots, const SysParams* prm,
                                 const SpeciesTable* tab, hipStream_t st) {
   if (waves == 0) {  // symmetric tile pairs
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((pair_sym_kernel<Real, C>), dim3(count), dim3(64 * kSymWaves), 0, st, items, base,
-                       slots, prm, tab);
+    if (heat_flux)
+      hipLaunchKernelGGL((pair_sym_kernel<Real, C, true>), dim3(count), dim3(64 * kSymWaves), 0, st, items,
+                         base, slots, prm, tab);
+    else
+      hipLaunchKernelGGL((pair_sym_kernel<Real, C, false>), dim3(count), dim3(64 * kSymWaves), 0, st, items,
+                         base, slots, prm, tab);
     return hipGetLastError();
   }
+  if (heat_flux) return hipErrorInvalidValue;   // heat flux runs on symmetric items only
   if constexpr (C <= 3) {
     if (waves == 4) return launch_pair_cw<Real, C, 4>(items, base, count, slots, prm, tab, st);
   }
   return launch_pair_cw<Real, C, 1>(items, base, count, slots, prm, tab, st);
 }
 
-hipError_t launch_pair(int cls, int precision, int waves, const WorkItem* items, int base,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, const WorkItem* items, int base,
                        int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st) {
-#define MS2_PAIR_CASE(C)                                                                        \
-  case C:                                                                                       \
-    return precision == MS2_FP32                                                                \
-               ? launch_pair_c<float, C>(waves, items, base, count, slots, prm, tab, st)        \
-               : launch_pair_c<double, C>(waves, items, base, count, slots, prm, tab, st);
+#define MS2_PAIR_CASE(C)                                                                                \
+  case C:                                                                                               \
+    return precision == MS2_FP32                                                                        \
+               ? launch_pair_c<float, C>(waves, heat_flux, items, base, count, slots, prm, tab, st)     \
+               : launch_pair_c<double, C>(waves, heat_flux, items, base, count, slots, prm, tab, st);
   switch (cls) {
     MS2_PAIR_CASE(0)
     MS2_PAIR_CASE(1)

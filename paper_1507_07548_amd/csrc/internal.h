@@ -15,7 +15,7 @@ struct KVec { int nx, ny, nz, n2; };
 
 constexpr int kMaxSp = MS2_MAX_SPECIES;
 constexpr int kMaxS = MS2_MAX_SITES;
-constexpr int kNumBlockSums = 6;  // u_lj, u_el, us, uss, npair, nsite per work item
+constexpr int kNumBlockSums = 9;  // u_lj, u_el, us, uss, npair, nsite, J_q pair part (x, y, z) per work item
 constexpr int kKChunk = 128;      // k vectors per reciprocal-force block
 constexpr int kMolTile = 64;      // molecules per structure-factor block
 constexpr int kMaxRdfTypes = 16;
@@ -87,6 +87,13 @@ struct SlotDev {
   int com_ld;                 // row length of com/quat/force/torque (and slot state) arrays
   int symmetric;              // 1: symmetric tile-pair items (each pair once)
   int pf_single;              // 1: pair partials in FP32 (the FP32 form), 0: FP64
+  int heat_flux;              // 1: the pair kernel adds the pair part of the heat flux
+  int pad_hf;
+  const double* hf_v;         // [3][com_ld] velocity source (x hf_vscale), heat flux only
+  const double* hf_w;         // [3][com_ld] body angular velocity, or NULL
+  double hf_vscale;
+  void* hf_kin;               // [6][npad] Real: lab v and w at the force evaluation
+  double* jq;                 // [3] pair part of the heat flux of the last evaluation
   const int* species;
   const double* com;          // [3][com_ld]
   const double* quat;         // [4][com_ld]
@@ -163,6 +170,14 @@ struct MDDev {
   int* res_inside;             // [n_solute] shell population now (staging)
   double* res_acf;             // [acf_nlag]
   double* res_cnt;             // [acf_nlag]
+  // heat-flux autocorrelation, on the ACF schedule
+  int hf_on, pad3;
+  double h_partial[kMaxSp];    // partial enthalpy per molecule of each species
+  double jq_now[3];            // J_q of this step's force evaluation
+  double* acf_q;               // [acf_nlag]
+  double* acf_q_cnt;           // [acf_nlag]
+  double* origin_jq;           // [acf_max_live][3]
+  int* origin_jq_valid;        // [acf_max_live]
 };
 
 // residence state word: the pair no longer counts for this origin

@@ -86,9 +86,10 @@ __global__ __launch_bounds__(256) void md_wrap_kernel(MDDev* md, const SysParams
   for (int c = 0; c < 3; ++c) m.r[c * n + i] = wrap(m.r[c * n + i], P.L, P.invL);
 }
 
-// ACF sample at the current state: v is [3][npad]
+// ACF sample at the current state: v is [3][npad].  have_jq: m.jq_now holds
+// this step's heat flux (there is none for the initial state).
 __device__ void acf_sample(MDDev& m, const SpeciesTable* tab, const SlotDev& sd, const double* v,
-                           int npad, long long s, double* red) {
+                           int npad, long long s, double* red, bool have_jq) {
   const int tid = threadIdx.x, n = sd.n;
   double jl[3] = {0, 0, 0};
   for (int i = tid; i < n; i += kMdThreads) {
@@ -105,6 +106,10 @@ __device__ void acf_sample(MDDev& m, const SpeciesTable* tab, const SlotDev& sd,
     if (tid == 0) {
       m.origin_t0[slot_o] = s;
       for (int c = 0; c < 3; ++c) m.origin_j[3 * slot_o + c] = j[c];
+      if (m.hf_on) {
+        m.origin_jq_valid[slot_o] = have_jq ? 1 : 0;
+        for (int c = 0; c < 3; ++c) m.origin_jq[3 * slot_o + c] = have_jq ? m.jq_now[c] : 0.0;
+      }
     }
     __syncthreads();
     if (tid == 0) m.n_origins += 1;
@@ -126,6 +131,11 @@ __device__ void acf_sample(MDDev& m, const SpeciesTable* tab, const SlotDev& sd,
       m.acf_j[lag] += m.origin_j[3 * o] * j[0] + m.origin_j[3 * o + 1] * j[1] +
                       m.origin_j[3 * o + 2] * j[2];
       m.acf_cnt[lag] += 1.0;
+      if (m.hf_on && have_jq && m.origin_jq_valid[o]) {
+        m.acf_q[lag] += m.origin_jq[3 * o] * m.jq_now[0] + m.origin_jq[3 * o + 1] * m.jq_now[1] +
+                        m.origin_jq[3 * o + 2] * m.jq_now[2];
+        m.acf_q_cnt[lag] += 1.0;
+      }
     }
   }
 }
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(kMdThreads) void md_init_kernel(SlotDev* slots, MDD
     m.ekin_tr = 0.5 * k2;
     m.ekin_rot = 0.5 * kr2;
   }
-  if (m.acf_every > 0) acf_sample(m, tab, sd, vnow, np, 0, red);
+  if (m.acf_every > 0) acf_sample(m, tab, sd, vnow, np, 0, red, false);
   if (tid == 0 && m.res_on) {
     m.res_due = 1;
     m.res_step = 0;
@@ -285,6 +295,29 @@ __global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDe
   const double ct[5] = {19.0 / 120.0, 3.0 / 4.0, 1.0, 1.0 / 2.0, 1.0 / 12.0};
   const double cr[5] = {251.0 / 720.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0};
   double* v = m.vel;
+  if (m.hf_on && m.acf_every > 0 && (m.steps_done + 1) % m.acf_every == 0) {
+    // heat flux of this step's force evaluation (still the predicted state):
+    // sum_k (m v^2/2 + w.I.w/2 - h_k) v_k plus the pair part from the pair kernel
+    double jk[3] = {0.0, 0.0, 0.0};
+    for (int i = tid; i < n; i += kMdThreads) {
+      const int spi = clamp_species(sd.species[i], tab->nsp);
+      const SpeciesDev& D = tab->sp[spi];
+      double vi[3], e = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        vi[c] = m.integrator == MS2_GEAR ? m.r[(1 * 3 + c) * np + i] / dt : v[c * np + i];
+        e += 0.5 * D.mass * vi[c] * vi[c];
+      }
+      if (m.integrator == MS2_GEAR && m.rotating)
+        for (int c = 0; c < 3; ++c) e += 0.5 * D.inertia[c] * m.w[c * np + i] * m.w[c * np + i];
+      e -= m.h_partial[spi];
+      for (int c = 0; c < 3; ++c) jk[c] += e * vi[c];
+    }
+    for (int c = 0; c < 3; ++c) {
+      const double t = block_sum(jk[c], red);
+      if (tid == 0) m.jq_now[c] = t + sd.jq[c];
+    }
+    __syncthreads();
+  }
   for (int i = tid; i < n; i += kMdThreads) {
     const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
     if (m.integrator == MS2_GEAR) {
@@ -378,7 +411,7 @@ __global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDe
     if (!ok) m.status = MS2_ENONFINITE;
   }
   if (m.acf_every > 0 && s % m.acf_every == 0) {
-    acf_sample(m, tab, sd, v, np, s, red);
+    acf_sample(m, tab, sd, v, np, s, red, true);
     if (tid == 0 && m.res_on) {
       m.res_due = 1;
       m.res_step = s;

@@ -55,6 +55,7 @@ class System(ctypes.Structure):
                 ("acf_origin_every", c_int32), ("acf_nlag", c_int32), ("rdf_rmax", c_double),
                 ("u0", c_double), ("res_enable", c_int32), ("res_solute", c_int32),
                 ("res_solvent", c_int32), ("res_tolerance", c_int32), ("res_radius", c_double),
+                ("heat_flux", c_int32), ("hf_pad", c_int32), ("h_partial", c_double * MAX_SPECIES),
                 ("h_species", P(c_int32)), ("h_com", P(c_double)),
                 ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double))]
 
@@ -65,7 +66,8 @@ class Samples(ctypes.Structure):
                 ("pairs_total", c_double), ("site_pairs_total", c_double), ("moments", c_double * 11),
                 ("solvation_sum", c_double), ("solvation_cnt", c_double), ("h_rdf", P(c_double)),
                 ("h_acf_v", P(c_double)), ("h_acf_j", P(c_double)), ("h_acf_cnt", P(c_double)),
-                ("h_res_acf", P(c_double)), ("h_res_cnt", P(c_double)), ("h_com", P(c_double)),
+                ("h_res_acf", P(c_double)), ("h_res_cnt", P(c_double)), ("h_acf_q", P(c_double)),
+                ("h_acf_q_cnt", P(c_double)), ("h_com", P(c_double)),
                 ("h_quat", P(c_double)), ("h_vel", P(c_double)), ("h_omega", P(c_double)),
                 ("h_force", P(c_double)), ("h_torque", P(c_double))]
 
@@ -257,6 +259,8 @@ def system_struct(system, precision: int, n_steps: Optional[int] = None):
                rdf_rmax=md.rdf_rmax, u0=md.u0, res_enable=1 if md.res_solute >= 0 else 0,
                res_solute=max(md.res_solute, 0), res_solvent=max(md.res_solvent, 0),
                res_radius=md.res_radius, res_tolerance=md.res_tolerance,
+               heat_flux=1 if md.heat_flux else 0,
+               h_partial=(c_double * MAX_SPECIES)(*(list(md.h_partial or ()) + [0.0] * MAX_SPECIES)[:MAX_SPECIES]),
                h_species=sp.ctypes.data_as(P(c_int32)), h_com=dp(com),
                h_quat=dp(quat), h_vel=dp(vel), h_omega=dp(om))
     return s, keep
@@ -339,6 +343,8 @@ class Batch:
             buf("acf_cnt", nlag)
             buf("res_acf", nlag)
             buf("res_cnt", nlag)
+            buf("acf_q", nlag)
+            buf("acf_q_cnt", nlag)
         if state:
             buf("com", (3, n))
             buf("quat", (4, n))
