@@ -163,6 +163,8 @@ def main():
                     help="launch the batched steps directly instead of through a hipGraph")
     ap.add_argument("--tile-shape", type=str, default=None,
                     help="waves,jchunk for every size bucket instead of autotuning (0,64 = symmetric)")
+    ap.add_argument("--heat-flux", action="store_true",
+                    help="sample the heat-flux ACF (extended step 10, origins every 100, 100 lags) on every system")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -187,6 +189,10 @@ def main():
         log(f"[bench] copied {nbytes} bytes device to device (counter calibration)")
         del src, dst
     systems = [inputs.batched_state_point(s) for s in range(args.systems)]
+    if args.heat_flux:
+        for s in systems:
+            s.md.acf_every, s.md.acf_origin_every, s.md.acf_nlag = 10, 100, 100
+            s.md.heat_flux = True
     ctx = ms2.Context(systems[0].species)
     tuned = None
     if args.tile_shape:
@@ -253,7 +259,8 @@ def main():
                    "n_range": [500, 4000], "density_range": [0.1, 0.8], "temperature_range": [1.0, 3.0],
                    "molecules": int(sum(s.n for s in systems)), "rc_over_box": 0.48,
                    "precision": "fp32 pairs, fp64 sums", "integrator": "gear-5 quaternion NVT",
-                   "moments_every": 1, "graph": graph, "tile_shapes_batched": tuned},
+                   "moments_every": 1, "graph": graph, "tile_shapes_batched": tuned,
+                   "heat_flux_acf": bool(args.heat_flux)},
         "md_steps_per_s": steps_per_s,
         "mol_pairs_per_step": mol_pairs / K,
         "site_pairs_per_step": site_pairs / K,
