@@ -38,7 +38,7 @@ class OrSpecies(ctypes.Structure):
 class OrParams(ctypes.Structure):
     _fields_ = [("box", c_double), ("rc", c_double), ("eps_rf", c_double), ("alpha", c_double),
                 ("coulomb_k", c_double), ("elec", c_int32), ("kmax2", c_int32),
-                ("lj_lrc", c_int32), ("pad", c_int32)]
+                ("lj_lrc", c_int32), ("cutoff_mode", c_int32)]
 
 
 class OrMD(ctypes.Structure):
@@ -105,7 +105,7 @@ def species_array(species) -> ctypes.Array:
 
 def params_struct(p) -> OrParams:
     return OrParams(box=p.box, rc=p.rc, eps_rf=p.eps_rf, alpha=p.alpha, coulomb_k=p.coulomb_k,
-                    elec=p.elec, kmax2=p.kmax2, lj_lrc=p.lj_lrc, pad=0)
+                    elec=p.elec, kmax2=p.kmax2, lj_lrc=p.lj_lrc, cutoff_mode=getattr(p, "cutoff_mode", 0))
 
 
 def _arrays(system):

@@ -92,12 +92,27 @@ static int is_elec(int t) { return t == OR_CHARGE || t == OR_DIPOLE || t == OR_Q
 /* ------------------------------------------------------------------ */
 /* argument checks                                                     */
 /* ------------------------------------------------------------------ */
+/* largest distance of an LJ site from its molecule's centre */
+static double lj_dmax(const or_species* sp, int nsp) {
+  double d = 0.0;
+  for (int s = 0; s < nsp; ++s)
+    for (int a = 0; a < sp[s].n_sites; ++a)
+      if (sp[s].type[a] == OR_LJ) {
+        double r = sqrt(sp[s].pos[a][0] * sp[s].pos[a][0] + sp[s].pos[a][1] * sp[s].pos[a][1] +
+                        sp[s].pos[a][2] * sp[s].pos[a][2]);
+        if (r > d) d = r;
+      }
+  return d;
+}
+
 int or_check(const or_species* sp, int32_t nsp, const or_params* p) {
   if (!sp || !p || nsp <= 0) return -1;
   if (!(p->box > 0.0) || !(p->rc > 0.0) || !(2.0 * p->rc < p->box)) return -2;
   if (p->elec < OR_ELEC_NONE || p->elec > OR_ELEC_EWALD) return -3;
   if (p->elec == OR_ELEC_RF && !(p->eps_rf >= 1.0)) return -4;
   if (p->elec == OR_ELEC_EWALD && (!(p->alpha > 0.0) || p->kmax2 < 1)) return -5;
+  if (p->cutoff_mode != OR_CUT_COM && p->cutoff_mode != OR_CUT_SITE) return -9;
+  if (p->cutoff_mode == OR_CUT_SITE && !(2.0 * (p->rc + 2.0 * lj_dmax(sp, nsp)) < p->box)) return -2;
   for (int s = 0; s < nsp; ++s) {
     if (sp[s].n_sites < 1 || sp[s].n_sites > OR_MAXS) return -6;
     for (int a = 0; a < sp[s].n_sites; ++a) {
@@ -248,14 +263,23 @@ static void multipole_terms(int ta, int tb, double ca, double cb, double cab,
 }
 
 /* One site pair (a on molecule i, b on molecule j) of an accepted pair. */
+/* One site pair of an accepted molecule pair.  elec_in: the molecule
+ * centres are inside the cut-off (electrostatic site pairs interact only
+ * then); in the site-site mode an LJ site pair interacts only when its own
+ * distance is inside the cut-off. */
 static void site_pair(const or_species* si, int a, const or_species* sj, int b,
                       const lab_t* li, const lab_t* lj, const double* R,
-                      const or_params* p, const rf_t* rf, pair_acc* o) {
+                      const or_params* p, const rf_t* rf, int elec_in, pair_acc* o) {
   int ta = si->type[a], tb = sj->type[b];
   const double* da = li->d[a];
   const double* db = lj->d[b];
   double rv[3];
   for (int k = 0; k < 3; ++k) rv[k] = R[k] + da[k] - db[k];
+  double r2s = rv[0] * rv[0];
+  r2s = r2s + rv[1] * rv[1];
+  r2s = r2s + rv[2] * rv[2];
+  if (ta == OR_LJ && tb == OR_LJ && p->cutoff_mode == OR_CUT_SITE && !(r2s < p->rc * p->rc)) return;
+  if (is_elec(ta) && is_elec(tb) && !elec_in) return;
   double r = sqrt(dot3(rv, rv));
 
   if (ta == OR_LJ && tb == OR_LJ) {
@@ -344,6 +368,8 @@ int or_forces(const or_species* sp, int32_t nsp, const or_params* p, int32_t n,
     if (species[i] < 0 || species[i] >= nsp) return -11;
 
   double L = p->box, rc2 = p->rc * p->rc;
+  int site_mode = p->cutoff_mode == OR_CUT_SITE;
+  double rs = p->rc + 2.0 * lj_dmax(sp, nsp), rs2 = rs * rs;
   rf_t rf = {0.0, 0.0};
   if (p->elec == OR_ELEC_RF) {
     rf.k_rf = isinf(p->eps_rf) ? 1.0 / (2.0 * p->rc * p->rc * p->rc)
@@ -367,14 +393,17 @@ int or_forces(const or_species* sp, int32_t nsp, const or_params* p, int32_t n,
         R[k] = d - L * rint(d / L);           /* minimum image */
       }
       double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-      if (!(r2 < rc2)) continue;              /* molecule-centre cut-off */
+      int elec_in = r2 < rc2;                  /* molecule-centre cut-off */
+      if (!site_mode && !elec_in) continue;
+      if (site_mode && !(r2 < rs2)) continue;   /* no LJ site pair can reach */
       pair_acc o;
       memset(&o, 0, sizeof(o));
       const or_species* si = &sp[species[i]];
       const or_species* sj = &sp[species[j]];
       for (int a = 0; a < si->n_sites; ++a)
         for (int b = 0; b < sj->n_sites; ++b)
-          site_pair(si, a, sj, b, &lab[i], &lab[j], R, p, &rf, &o);
+          site_pair(si, a, sj, b, &lab[i], &lab[j], R, p, &rf, elec_in, &o);
+      if (site_mode && o.nsite == 0.0) continue;  /* no site pair interacts */
       for (int k = 0; k < 3; ++k) {
         force[3 * i + k] += o.f[k];
         force[3 * j + k] -= o.f[k];
@@ -463,14 +492,15 @@ int or_heat_flux(const or_species* sp, int32_t nsp, const or_params* p, int32_t 
         R[k] = d - L * rint(d / L);
       }
       double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-      if (!(r2 < rc2)) continue;
+      int elec_in = r2 < rc2;
+      if (p->cutoff_mode == OR_CUT_COM && !elec_in) continue;
       pair_acc o;
       memset(&o, 0, sizeof(o));
       const or_species* si = &sp[species[i]];
       const or_species* sj = &sp[species[j]];
       for (int a = 0; a < si->n_sites; ++a)
         for (int b = 0; b < sj->n_sites; ++b)
-          site_pair(si, a, sj, b, &lab[i], &lab[j], R, p, &rf, &o);
+          site_pair(si, a, sj, b, &lab[i], &lab[j], R, p, &rf, elec_in, &o);
       double u = o.u_lj + o.u_el, vs[3];
       for (int k = 0; k < 3; ++k) vs[k] = vel[3 * i + k] + vel[3 * j + k];
       double power = dot3(o.f, vs) + dot3(o.ti, wlab + 3 * i) - dot3(o.tj, wlab + 3 * j);

@@ -73,8 +73,14 @@ typedef struct {
   int32_t elec;      /* OR_ELEC_*                              */
   int32_t kmax2;     /* Ewald: integer vectors 0 < n^2 <= kmax2 */
   int32_t lj_lrc;    /* 1: add the LJ long-range correction    */
-  int32_t pad;
+  int32_t cutoff_mode; /* OR_CUT_COM: every site pair of molecules whose
+                          centres are closer than rc; OR_CUT_SITE: LJ site
+                          pairs closer than rc themselves, electrostatic
+                          site pairs of molecules closer than rc (needs
+                          rc + 2 dmax < L/2, dmax = largest LJ-site offset) */
 } or_params;
+
+enum { OR_CUT_COM = 0, OR_CUT_SITE = 1 };
 
 typedef struct {
   int32_t integrator;       /* OR_VV (point molecules only) or OR_GEAR */

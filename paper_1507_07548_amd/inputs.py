@@ -22,6 +22,7 @@ import numpy as np
 
 LJ, CHARGE, DIPOLE, QUAD = 0, 1, 2, 3
 ELEC_NONE, ELEC_RF, ELEC_EWALD = 0, 1, 2
+CUT_COM, CUT_SITE = 0, 1
 VV, GEAR = 0, 1
 
 # e^2 / (4 pi eps0 k_B Angstrom): Coulomb constant for energies in K,
@@ -60,6 +61,7 @@ class Params:
     kmax2: int = 0
     coulomb_k: float = 1.0
     lj_lrc: int = 1
+    cutoff_mode: int = 0            # CUT_COM or CUT_SITE (LJ site pairs cut at their own distance)
 
 
 @dataclasses.dataclass
