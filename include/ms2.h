@@ -50,6 +50,7 @@ typedef enum {
 enum { MS2_SITE_LJ = 0, MS2_SITE_CHARGE = 1, MS2_SITE_DIPOLE = 2, MS2_SITE_QUAD = 3 };
 enum { MS2_ELEC_NONE = 0, MS2_ELEC_RF = 1, MS2_ELEC_EWALD = 2 };
 enum { MS2_FP64 = 0, MS2_FP32 = 1 };           /* pair arithmetic precision */
+enum { MS2_CUT_COM = 0, MS2_CUT_SITE = 1 };    /* ms2_params.cutoff_mode    */
 enum { MS2_VV = 0, MS2_GEAR = 1 };
 
 /* Slots of the double sums[MS2_NSUM] output.
@@ -98,7 +99,7 @@ typedef struct {
 /* Per-system physical parameters (host memory, read before return). */
 typedef struct {
   double box;        /* cubic edge L                                        */
-  double rc;         /* molecule-centre cut-off, 0 < rc < L/2               */
+  double rc;         /* cut-off radius, 0 < rc < L/2 (see cutoff_mode)      */
   double eps_rf;     /* reaction-field permittivity, >= 1, INFINITY allowed */
   double alpha;      /* Ewald splitting parameter (> 0 with Ewald)          */
   double coulomb_k;  /* 1/(4 pi eps0)                                       */
@@ -106,6 +107,15 @@ typedef struct {
   int32_t kmax2;     /* Ewald k set: integer n with 0 < |n|^2 <= kmax2      */
   int32_t lj_lrc;    /* 1: LJ long-range correction (Sec. 3)                */
   int32_t precision; /* MS2_FP64 or MS2_FP32 (FP32 pairs, FP64 sums)         */
+  int32_t cutoff_mode; /* MS2_CUT_COM: a molecule pair interacts (all its site
+                          pairs) when its centres are closer than rc.
+                          MS2_CUT_SITE: an LJ site pair interacts when its
+                          own distance is below rc; electrostatic site pairs
+                          still follow the centre distance; needs
+                          rc + 2 d_max < L/2, d_max the largest LJ-site
+                          distance from a centre (Sec. 3).  The LJ long-range
+                          correction is the same in both modes.            */
+  int32_t pad;       /* set to 0                                           */
 } ms2_params;
 
 typedef struct ms2_ctx ms2_ctx;

@@ -20,8 +20,8 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, const WorkItem* items, int base,
-                       int count, const SlotDev* slots, const SysParams* prm,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, const WorkItem* items,
+                       int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st);
@@ -175,6 +175,17 @@ static int pick_class(const SpeciesTable& t) {
 // ---------------------------------------------------------------------------
 // per-system constants
 // ---------------------------------------------------------------------------
+// largest distance of an LJ site from its molecule's centre
+double lj_extent(const ms2_ctx* ctx) {
+  double d = 0.0;
+  for (int s = 0; s < ctx->tab.nsp; ++s)
+    for (int a = 0; a < ctx->tab.sp[s].nlj; ++a) {
+      const double* r = ctx->tab.sp[s].lj_pos[a];
+      d = std::max(d, std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+    }
+  return d;
+}
+
 ms2_status check_params(const ms2_ctx* ctx, const ms2_params* p) {
   if (!p) return set_error(MS2_EINVAL, "params is NULL");
   if (!(p->box > 0.0) || !std::isfinite(p->box)) return set_error(MS2_EINVAL, "box must be > 0");
@@ -185,6 +196,10 @@ ms2_status check_params(const ms2_ctx* ctx, const ms2_params* p) {
   if (p->precision != MS2_FP64 && p->precision != MS2_FP32)
     return set_error(MS2_EINVAL, "precision must be MS2_FP64 or MS2_FP32");
   if (!std::isfinite(p->coulomb_k)) return set_error(MS2_EINVAL, "coulomb_k must be finite");
+  if (p->cutoff_mode != MS2_CUT_COM && p->cutoff_mode != MS2_CUT_SITE)
+    return set_error(MS2_EINVAL, "cutoff_mode must be MS2_CUT_COM or MS2_CUT_SITE");
+  if (p->cutoff_mode == MS2_CUT_SITE && !(2.0 * (p->rc + 2.0 * lj_extent(ctx)) < p->box))
+    return set_error(MS2_EINVAL, "site-site cut-off needs rc + 2 d_max < box/2 (d_max: largest LJ-site offset)");
   if (p->elec == MS2_ELEC_RF && !(p->eps_rf >= 1.0))
     return set_error(MS2_EINVAL, "reaction field needs eps_rf >= 1");
   if (p->elec == MS2_ELEC_EWALD) {
@@ -213,6 +228,15 @@ void build_sys_params(const ms2_ctx* ctx, const ms2_params* p, int nk, SysParams
   s.precision = p->precision;
   s.cls = ctx->cls;
   s.nsp = ctx->tab.nsp;
+  s.site_cut = p->cutoff_mode == MS2_CUT_SITE ? 1 : 0;
+  if (s.site_cut) {
+    // no LJ site pair of centres farther apart than rc + 2 d_max can be
+    // closer than rc
+    const double rs = p->rc + 2.0 * lj_extent(ctx);
+    s.rc2_search = rs * rs;
+  } else {
+    s.rc2_search = s.rc2;
+  }
   const double rc3 = p->rc * p->rc * p->rc;
   if (p->elec == MS2_ELEC_RF) {
     s.krf = std::isinf(p->eps_rf) ? 0.5 / rc3 : (p->eps_rf - 1.0) / ((2.0 * p->eps_rf + 1.0) * rc3);
@@ -366,7 +390,11 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
     return set_error(MS2_EINVAL, "ms2_ewald_kspace needs elec == MS2_ELEC_EWALD");
   MS2_HIP(hipSetDevice(ctx->device));
   const int npad = (n + 63) & ~63;
-  const TileCfg cfg = tile_config(ctx, 0, p->precision, n);
+  TileCfg cfg = tile_config(ctx, 0, p->precision, n);
+  if (p->cutoff_mode == MS2_CUT_SITE) {   // the site-site cut-off runs on symmetric items only
+    cfg.waves = 0;
+    cfg.jchunk = 64;
+  }
   const int rs = p->precision == MS2_FP32 ? 4 : 8;
 
   // items (cached per n and tile shape)
@@ -532,7 +560,8 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
   if (s != MS2_OK) return s;
   const ms2::CachedItems& ci = ctx->item_cache[std::make_tuple(n_mol, cfg.waves, cfg.jchunk)];
   MS2_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n_mol, st));
-  MS2_HIP(launch_pair(ctx->cls, h_params->precision, cfg.waves, false, (const WorkItem*)ci.buf.p, 0, nitems,
+  MS2_HIP(launch_pair(ctx->cls, h_params->precision, cfg.waves, false, h_params->cutoff_mode == MS2_CUT_SITE,
+                      (const WorkItem*)ci.buf.p, 0, nitems,
                       r->d_slot, r->d_prm, ctx->d_tab, st));
   MS2_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, n_mol, st));
   MS2_HIP(hipEventRecord(r->ev, st));

@@ -23,8 +23,8 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, const WorkItem* items, int base,
-                       int count, const SlotDev* slots, const SysParams* prm,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, const WorkItem* items,
+                       int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st);
@@ -70,6 +70,7 @@ struct SlotShape {
   int rdf_ntp, rdf_bins, acf_nlag, acf_max_live;
   int n_solute, n_solvent;   // residence sampling (0 = off)
   int heat_flux;             // heat-flux ACF (symmetric items)
+  int site_cut;              // site-site cut-off mode (symmetric items)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -161,7 +162,7 @@ struct ms2_batch {
   std::vector<SlotHost> slots;
   DevBuf d_slots, d_md, d_prm, d_items;
   // work items grouped by (precision, waves): [begin, end) into d_items
-  struct Group { int precision, waves, begin, end; bool heat_flux; };
+  struct Group { int precision, waves, begin, end; bool heat_flux, site_cut; };
   std::vector<Group> groups;
   bool dirty = true;
   int max_n = 2, max_kblocks = 1, max_mchunks = 1, max_mtiles = 1, max_kchunks = 1;
@@ -220,7 +221,8 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
   s.precision = sys->params.precision;
   s.mode = mode;
   TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
-  if (sys->heat_flux) {    // the heat-flux pair part is evaluated on symmetric items only
+  s.site_cut = sys->params.cutoff_mode == MS2_CUT_SITE ? 1 : 0;
+  if (sys->heat_flux || s.site_cut) {   // both are evaluated on symmetric items only
     cfg.waves = 0;
     cfg.jchunk = 64;
   }
@@ -291,11 +293,14 @@ void rebuild_items(ms2_batch* b) {
   b->max_solute = 0;
   for (int prec : {MS2_FP64, MS2_FP32})
     for (int hfv : {0, 1})
+    for (int scv : {0, 1})
     for (int waves : {0, 1, 4}) {
-      ms2_batch::Group g{prec, waves, (int)all.size(), 0, hfv == 1};
+      ms2_batch::Group g{prec, waves, (int)all.size(), 0, hfv == 1, scv == 1};
       for (int s = 0; s < b->max_slots; ++s) {
         const SlotHost& h = b->slots[s];
-        if (!h.used || h.shape.precision != prec || h.shape.waves != waves || h.shape.heat_flux != hfv) continue;
+        if (!h.used || h.shape.precision != prec || h.shape.waves != waves || h.shape.heat_flux != hfv ||
+            h.shape.site_cut != scv)
+          continue;
         TileCfg c;
         c.waves = h.shape.waves;
         c.jchunk = h.shape.jchunk;
@@ -342,8 +347,8 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
   }
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_begin[timed_step], st));
   for (auto& g : b->groups)
-    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, di, g.begin, g.end - g.begin, ds, dp, ctx->d_tab,
-                        st));
+    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, di, g.begin, g.end - g.begin, ds,
+                        dp, ctx->d_tab, st));
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
   MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
   if (b->any_ewald)

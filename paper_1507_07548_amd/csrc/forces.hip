@@ -332,7 +332,7 @@ struct SymFinal {
   double sums[kSymWaves][kNumBlockSums];
 };
 
-template <typename Real, int C, bool HF>
+template <typename Real, int C, bool HF, bool SITE>
 __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   int item_base,
                                                                   const SlotDev* __restrict__ slots,
@@ -363,6 +363,9 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
 
   const int n = sd.n, ld = sd.com_ld, np = sd.npad;
   const double L = P.L, invL = P.invL, rc2 = P.rc2;
+  // pairs are listed within the centre cut-off, or in the site-site mode
+  // within the radius at which an LJ site pair can still reach
+  const double rlist2 = SITE ? P.rc2_search : rc2;
   const ElecParams<Real> E = elec_params<Real>(P);
   const Real* __restrict__ gsite = reinterpret_cast<const Real*>(sd.sites);
   const bool diag = it.i0 == it.j0;
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
       double dx, dy, dz, r2;
       min_image(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L, invL, dx, dy, dz,
                 r2);
-      const unsigned ok = (unsigned)(r2 < rc2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
+      const unsigned ok = (unsigned)(r2 < rlist2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
       part |= ok << b;
     }
     s_mpart[wv][lane] = lane < nrow ? part : 0u;
@@ -480,8 +483,17 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     PairAcc<Real> acc{0, 0, 0, 0, 0, 0};
     SiteAcc<Real, C> ai, unused;
     ai.zero();
-    eval_molecule_pair<Real, C, false, TJ>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry, Rz, R2,
-                                           ai, unused, acc);
+    const bool elec_in = !SITE || r2d < rc2;
+    int nlj_in = 0;
+    eval_molecule_pair<Real, C, false, TJ, SITE>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry, Rz,
+                                                 R2, ai, unused, acc, (Real)rc2, elec_in, &nlj_in);
+    // interacting site pairs; in the site-site mode a listed pair counts
+    // only when at least one of its site pairs interacts
+    int ns = s_tab.nsite[spi][spj];
+    if constexpr (SITE) {
+      const int nlj2 = s_tab.cnt[spi][0] * s_tab.cnt[spj][0];
+      ns = nlj_in + (elec_in ? ns - nlj2 : 0);
+    }
     Real Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0};
     fold_sites<Real, C, 1, Real>(rec, ai, Fi, Ti);
     const Real Tj[3] = {-Ti[0] - (Ry * Fi[2] - Rz * Fi[1]), -Ti[1] - (Rz * Fi[0] - Rx * Fi[2]),
@@ -491,8 +503,8 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
       a_uel += (double)acc.uel;
       a_uss += (double)acc.uss;
       a_us -= (double)(Rx * acc.fx + Ry * acc.fy + Rz * acc.fz);
-      a_np += 1;
-      a_ns += s_tab.nsite[spi][spj];
+      a_np += (!SITE || ns > 0) ? 1 : 0;
+      a_ns += ns;
       if constexpr (HF) {
         // pair part of the heat flux: u (v_i + v_j)/2 + R (F.(v_i + v_j) +
         // tau_i.w_i - tau_j.w_j)/2
@@ -721,35 +733,42 @@ static hipError_t launch_pair_cw(const WorkItem* items, int base, int count, con
   return hipGetLastError();
 }
 
+template <typename Real, int C, bool HF, bool SITE>
+static hipError_t launch_pair_sym(const WorkItem* items, int base, int count, const SlotDev* slots,
+                                  const SysParams* prm, const SpeciesTable* tab, hipStream_t st) {
+  hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE>), dim3(count), dim3(64 * kSymWaves), 0, st, items,
+                     base, slots, prm, tab);
+  return hipGetLastError();
+}
+
 template <typename Real, int C>
-static hipError_t launch_pair_c(int waves, bool heat_flux, const WorkItem* items, int base, int count,
-                                const SlotDev* slots, const SysParams* prm,
+static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, const WorkItem* items, int base,
+                                int count, const SlotDev* slots, const SysParams* prm,
                                 const SpeciesTable* tab, hipStream_t st) {
   if (waves == 0) {  // symmetric tile pairs
     if (count <= 0) return hipSuccess;
-    if (heat_flux)
-      hipLaunchKernelGGL((pair_sym_kernel<Real, C, true>), dim3(count), dim3(64 * kSymWaves), 0, st, items,
-                         base, slots, prm, tab);
-    else
-      hipLaunchKernelGGL((pair_sym_kernel<Real, C, false>), dim3(count), dim3(64 * kSymWaves), 0, st, items,
-                         base, slots, prm, tab);
-    return hipGetLastError();
+    if (site_cut)
+      return heat_flux ? launch_pair_sym<Real, C, true, true>(items, base, count, slots, prm, tab, st)
+                       : launch_pair_sym<Real, C, false, true>(items, base, count, slots, prm, tab, st);
+    return heat_flux ? launch_pair_sym<Real, C, true, false>(items, base, count, slots, prm, tab, st)
+                     : launch_pair_sym<Real, C, false, false>(items, base, count, slots, prm, tab, st);
   }
-  if (heat_flux) return hipErrorInvalidValue;   // heat flux runs on symmetric items only
+  // the heat flux and the site-site cut-off run on symmetric items only
+  if (heat_flux || site_cut) return hipErrorInvalidValue;
   if constexpr (C <= 3) {
     if (waves == 4) return launch_pair_cw<Real, C, 4>(items, base, count, slots, prm, tab, st);
   }
   return launch_pair_cw<Real, C, 1>(items, base, count, slots, prm, tab, st);
 }
 
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, const WorkItem* items, int base,
-                       int count, const SlotDev* slots, const SysParams* prm,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, const WorkItem* items,
+                       int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st) {
-#define MS2_PAIR_CASE(C)                                                                                \
-  case C:                                                                                               \
-    return precision == MS2_FP32                                                                        \
-               ? launch_pair_c<float, C>(waves, heat_flux, items, base, count, slots, prm, tab, st)     \
-               : launch_pair_c<double, C>(waves, heat_flux, items, base, count, slots, prm, tab, st);
+#define MS2_PAIR_CASE(C)                                                                                       \
+  case C:                                                                                                      \
+    return precision == MS2_FP32                                                                               \
+               ? launch_pair_c<float, C>(waves, heat_flux, site_cut, items, base, count, slots, prm, tab, st)  \
+               : launch_pair_c<double, C>(waves, heat_flux, site_cut, items, base, count, slots, prm, tab, st);
   switch (cls) {
     MS2_PAIR_CASE(0)
     MS2_PAIR_CASE(1)

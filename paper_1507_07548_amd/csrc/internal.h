@@ -72,7 +72,9 @@ struct SysParams {
   double ke, krf, crf;
   double alpha, alpha2, gpref;                     // gpref = 2 alpha / sqrt(pi)
   int elec, kmax2, nk, lrc;
-  int precision, cls, nsp, pad;
+  int precision, cls, nsp;
+  int site_cut;                                    // 1: LJ site pairs cut at their own distance
+  double rc2_search;                               // squared centre distance a pair needs to be listed
   // LJ tail per species pair: multiply by N_A N_B (already includes 2 pi / V)
   double lrc_u[kMaxSp][kMaxSp], lrc_us[kMaxSp][kMaxSp], lrc_uss[kMaxSp][kMaxSp];
   double ew_const[kMaxSp];                         // self + intramolecular per molecule

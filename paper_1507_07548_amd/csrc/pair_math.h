@@ -293,12 +293,18 @@ struct ElecParams {
 // i's sites go to ai; with JSIDE those on j's sites go to aj (force on a j
 // site is minus the force on its partner).  acc collects the pair's energy,
 // total force on i and d2U/ds2.
-template <typename Real, int C, bool JSIDE, int STRIDE>
+// SITE: the site-site cut-off mode.  An LJ site pair then interacts only
+// when its own squared distance is below lj_rc2 (and adds one to *nlj_in),
+// and the electrostatic site pairs only when elec_in (the centres inside the
+// cut-off).  Without SITE every site pair of the molecule pair interacts.
+template <typename Real, int C, bool JSIDE, int STRIDE, bool SITE = false>
 __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* sj, int spi, int spj,
                                                    const PairTables<Real, C>& T,
                                                    const ElecParams<Real>& E, Real Rx, Real Ry,
                                                    Real Rz, Real R2, SiteAcc<Real, C>& ai,
-                                                   SiteAcc<Real, C>& aj, PairAcc<Real>& acc) {
+                                                   SiteAcc<Real, C>& aj, PairAcc<Real>& acc,
+                                                   Real lj_rc2 = Real(0), bool elec_in = true,
+                                                   int* nlj_in = nullptr) {
   constexpr ClassShape S = kClassShapes[C];
   constexpr int NLJ = SiteAcc<Real, C>::NLJ;
   constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
@@ -320,8 +326,14 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
       const Real r2 = rx * rx + ry * ry + rz * rz;
       const Real ir2 = rcp_(r2);
       const Real ir6 = ir2 * ir2 * ir2;
-      const Real t6 = T.c6[spi * NLJ + a][spj * NLJ + b] * ir6;
-      const Real t12 = T.c12[spi * NLJ + a][spj * NLJ + b] * ir6 * ir6;
+      Real t6 = T.c6[spi * NLJ + a][spj * NLJ + b] * ir6;
+      Real t12 = T.c12[spi * NLJ + a][spj * NLJ + b] * ir6 * ir6;
+      if constexpr (SITE) {
+        const bool in = r2 < lj_rc2;
+        *nlj_in += in ? 1 : 0;
+        t6 = in ? t6 : Real(0);
+        t12 = in ? t12 : Real(0);
+      }
       const Real dur = (Real(6) * t6 - Real(12) * t12) * ir2;       // u'/r
       const Real d2u = (Real(156) * t12 - Real(42) * t6) * ir2;     // u''
       const Real rR = rx * Rx + ry * Ry + rz * Rz;
@@ -333,6 +345,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
       acc.fx += fx; acc.fy += fy; acc.fz += fz;
     }
   }
+  if (SITE && !elec_in) return;
   // charge-charge site pairs
   if constexpr (S.ch > 0) {
 #pragma unroll

@@ -45,7 +45,7 @@ class Species(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("box", c_double), ("rc", c_double), ("eps_rf", c_double), ("alpha", c_double),
                 ("coulomb_k", c_double), ("elec", c_int32), ("kmax2", c_int32), ("lj_lrc", c_int32),
-                ("precision", c_int32)]
+                ("precision", c_int32), ("cutoff_mode", c_int32), ("pad", c_int32)]
 
 
 class System(ctypes.Structure):
@@ -148,7 +148,8 @@ def species_array(species) -> ctypes.Array:
 
 def params_struct(p, precision: int) -> Params:
     return Params(box=p.box, rc=p.rc, eps_rf=p.eps_rf, alpha=p.alpha, coulomb_k=p.coulomb_k,
-                  elec=p.elec, kmax2=p.kmax2, lj_lrc=p.lj_lrc, precision=precision)
+                  elec=p.elec, kmax2=p.kmax2, lj_lrc=p.lj_lrc, precision=precision,
+                  cutoff_mode=getattr(p, "cutoff_mode", 0))
 
 
 def _stream_ptr(stream) -> Optional[int]:
