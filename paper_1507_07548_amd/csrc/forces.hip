@@ -298,11 +298,12 @@ constexpr int kSymWaves = 4;
 // Index in the chunk [q, q + 64) of this lane's row on a diagonal with word
 // wd starting at offset o - q (all wave-uniform), or -1 if the row is not on
 // it or its entry lies outside the chunk.
-__device__ __forceinline__ int row_entry(unsigned long long wd, int o_rel, int lane) {
+__device__ __forceinline__ int row_entry(unsigned long long wd, int o_rel) {
   const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(wd >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)wd, 0u));
   const int e = o_rel + rank;
-  const bool on = ((wd >> lane) & 1ull) != 0ull;
-  return (on && e >= 0 && e < 64) ? e : -1;
+  // wd is wave-uniform: its bits are the lane mask of the rows it holds
+  const bool on = __builtin_amdgcn_inverse_ballot_w64(wd);
+  return (on && (unsigned)e < 64u) ? e : -1;
 }
 
 __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
@@ -350,6 +351,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
   __shared__ unsigned s_mpart[NW][TJ];
   __shared__ unsigned long long s_dw[TJ];
   __shared__ int s_list[NW][TJ];          // per wave: row | diagonal << 6 of each entry of the chunk
+  __shared__ int s_inbox[2];              // 1: every staged centre of the side lies in [0, L]
 
   const WorkItem it = items[item_base + blockIdx.x];
   const SlotDev& sd = slots[it.slot];
@@ -382,9 +384,15 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
 #pragma unroll
       for (int c = 0; c < 3; ++c) c3[c] = sd.com[c * ld + mc];
       const int sp = lane < cnt ? clamp_species(sd.species[mc], nsp) : 0;
+      bool in = true;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) u.t.com[side][c][lane] = c3[c];
+      for (int c = 0; c < 3; ++c) {
+        u.t.com[side][c][lane] = c3[c];
+        in = in && c3[c] >= 0.0 && c3[c] <= L;
+      }
       s_sp[side][lane] = sp;
+      const bool all_in = __builtin_amdgcn_ballot_w64(!in) == 0ull;
+      if (lane == 0) s_inbox[side] = all_in ? 1 : 0;
     } else {
       Real r[NR];
 #pragma unroll
@@ -407,16 +415,27 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
   __syncthreads();
 
   // 1. cut-off bits: wave wv tests columns [16 wv, 16 wv + 16) of row `lane`
+  //    (centres in [0, L], the usual case: the image-free form of the same r2)
   {
     const double xi = u.t.com[0][0][lane], yi = u.t.com[0][1][lane], zi = u.t.com[0][2][lane];
+    const bool inbox = __builtin_amdgcn_readfirstlane(s_inbox[0] & s_inbox[1]) != 0;
     unsigned part = 0;
-    for (int b = 0; b < 16; ++b) {
-      const int jj = 16 * wv + b;
-      double dx, dy, dz, r2;
-      min_image(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L, invL, dx, dy, dz,
-                r2);
-      const unsigned ok = (unsigned)(r2 < rlist2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
-      part |= ok << b;
+    if (inbox) {
+      for (int b = 0; b < 16; ++b) {
+        const int jj = 16 * wv + b;
+        const double r2 = min_image_r2(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L);
+        const unsigned ok = (unsigned)(r2 < rlist2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
+        part |= ok << b;
+      }
+    } else {
+      for (int b = 0; b < 16; ++b) {
+        const int jj = 16 * wv + b;
+        double dx, dy, dz, r2;
+        min_image(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L, invL, dx, dy, dz,
+                  r2);
+        const unsigned ok = (unsigned)(r2 < rlist2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
+        part |= ok << b;
+      }
     }
     s_mpart[wv][lane] = lane < nrow ? part : 0u;
   }
@@ -428,10 +447,12 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
 #pragma unroll
     for (int w = 0; w < NW; ++w) m |= (unsigned long long)s_mpart[w][lane] << (16 * w);
     m = lane == 0 ? m : ((m >> lane) | (m << (TJ - lane)));
+    // this wave's 16 diagonals lie in one 32-bit half of m
+    const unsigned half = wv < 2 ? (unsigned)m : (unsigned)(m >> 32);
+    const int sh = 16 * (wv & 1);
     for (int b = 0; b < 16; ++b) {
-      const int d = 16 * wv + b;
-      const unsigned long long w = __builtin_amdgcn_ballot_w64(((m >> d) & 1ull) != 0ull);
-      if (lane == b) s_dw[d] = w;
+      const unsigned long long w = __builtin_amdgcn_ballot_w64(((half >> (sh + b)) & 1u) != 0u);
+      if (lane == 0) s_dw[16 * wv + b] = w;
     }
   }
   __syncthreads();
@@ -463,7 +484,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     int dlast = dfirst;
     while (dlast < TJ - 1 && __builtin_amdgcn_readlane(doff, dlast + 1) < qend) ++dlast;
     for (int dd = dfirst; dd <= dlast; ++dd) {
-      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q, lane);
+      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
       if (er >= 0) list[er] = lane | (dd << 6);
     }
     wave_sync_lds();
@@ -480,7 +501,8 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     Real rec[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) rec[k] = u.t.site[0][k][row];
-    PairAcc<Real> acc{0, 0, 0, 0, 0, 0};
+    constexpr Real z = -Real(0);             // -0 + x is x: no zeroing, no first add
+    PairAcc<Real> acc{z, z, z, z, z, z};
     SiteAcc<Real, C> ai, unused;
     ai.zero();
     const bool elec_in = !SITE || r2d < rc2;
@@ -494,7 +516,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
       const int nlj2 = s_tab.cnt[spi][0] * s_tab.cnt[spj][0];
       ns = nlj_in + (elec_in ? ns - nlj2 : 0);
     }
-    Real Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0};
+    Real Fi[3] = {z, z, z}, Ti[3] = {z, z, z};
     fold_sites<Real, C, 1, Real>(rec, ai, Fi, Ti);
     const Real Tj[3] = {-Ti[0] - (Ry * Fi[2] - Rz * Fi[1]), -Ti[1] - (Rz * Fi[0] - Rx * Fi[2]),
                         -Ti[2] - (Rx * Fi[1] - Ry * Fi[0])};
@@ -502,7 +524,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
       a_ulj += (double)acc.ulj;
       a_uel += (double)acc.uel;
       a_uss += (double)acc.uss;
-      a_us -= (double)(Rx * acc.fx + Ry * acc.fy + Rz * acc.fz);
+      a_us -= (double)(Rx * Fi[0] + Ry * Fi[1] + Rz * Fi[2]);
       a_np += (!SITE || ns > 0) ? 1 : 0;
       a_ns += ns;
       if constexpr (HF) {
@@ -533,7 +555,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     // gather: molecule `lane` of tile I at its own entry index; molecule
     // `lane` of tile J is the column of row lane - dd
     for (int dd = dfirst; dd <= dlast; ++dd) {
-      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q, lane);
+      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
       const int ec = __shfl(er, (lane - dd) & (TJ - 1), TJ);
       if (er >= 0) {
 #pragma unroll

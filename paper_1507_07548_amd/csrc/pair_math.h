@@ -47,6 +47,20 @@ __device__ __forceinline__ void min_image(double xi, double yi, double zi, doubl
   r2 = dx * dx + dy * dy + dz * dz;
 }
 
+// Squared minimum-image distance only, for centres wrapped into [0, L): a
+// component difference d lies in (-L, L) and its minimum-image magnitude is
+// min(|d|, L - |d|), with L - |d| rounded exactly as |d - L sign(d)|.  The
+// value equals min_image's r2 bit for bit wherever the nearest image is
+// unique (|d| not within rounding of L/2, where the component alone exceeds
+// any admissible cut-off).
+__device__ __forceinline__ double min_image_r2(double xi, double yi, double zi, double xj, double yj,
+                                               double zj, double L) {
+#pragma clang fp contract(off)
+  const double ax = fabs(xi - xj), ay = fabs(yi - yj), az = fabs(zi - zj);
+  const double mx = fmin(ax, L - ax), my = fmin(ay, L - ay), mz = fmin(az, L - az);
+  return mx * mx + my * my + mz * mz;
+}
+
 // ---------------------------------------------------------------------------
 // Orientation-dependent Coulomb terms of point multipoles.
 // u = K * P(ca, cb, cab) * r^-p with ca = ea.n, cb = eb.n, cab = ea.eb and n
@@ -233,17 +247,21 @@ struct SiteAcc {
   static constexpr int NLJ = S.lj > 0 ? S.lj : 1, NCH = S.ch > 0 ? S.ch : 1;
   static constexpr int NDP = S.dp > 0 ? S.dp : 1, NQD = S.qd > 0 ? S.qd : 1;
   Real fl[NLJ][3], fc[NCH][3], fd[NDP][3], gd[NDP][3], fq[NQD][3], gq[NQD][3];
+  // Sums start at -0: -0 + x is x for every x, so the compiler drops the
+  // first addition and the zeroing move (it may not drop +0 + x, which
+  // turns -0 into +0).
   __device__ __forceinline__ void zero() {
+    constexpr Real z = -Real(0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int a = 0; a < NLJ; ++a) fl[a][c] = 0;
+      for (int a = 0; a < NLJ; ++a) fl[a][c] = z;
 #pragma unroll
-      for (int a = 0; a < NCH; ++a) fc[a][c] = 0;
+      for (int a = 0; a < NCH; ++a) fc[a][c] = z;
 #pragma unroll
-      for (int a = 0; a < NDP; ++a) { fd[a][c] = 0; gd[a][c] = 0; }
+      for (int a = 0; a < NDP; ++a) { fd[a][c] = z; gd[a][c] = z; }
 #pragma unroll
-      for (int a = 0; a < NQD; ++a) { fq[a][c] = 0; gq[a][c] = 0; }
+      for (int a = 0; a < NQD; ++a) { fq[a][c] = z; gq[a][c] = z; }
     }
   }
 };
@@ -536,10 +554,19 @@ __device__ __forceinline__ void fold_sites(const Real* rec, const SiteAcc<Real, 
   for (int k = 0; k < S.lj; ++k) fold(3 * k, a.fl[k]);
 #pragma unroll
   for (int k = 0; k < S.ch; ++k) fold(OFF_CH + 3 * k, a.fc[k]);
+  // dipoles and quadrupoles of a central class sit at the centre: their
+  // forces exert no torque about it
+  auto fold_mp = [&](int off, const Real* f) {
+    if constexpr (S.central) {
+      F[0] += (Out)f[0]; F[1] += (Out)f[1]; F[2] += (Out)f[2];
+    } else {
+      fold(off, f);
+    }
+  };
 #pragma unroll
-  for (int k = 0; k < S.dp; ++k) { fold(OFF_DP + 6 * k, a.fd[k]); fold_g(OFF_DP + 6 * k + 3, a.gd[k]); }
+  for (int k = 0; k < S.dp; ++k) { fold_mp(OFF_DP + 6 * k, a.fd[k]); fold_g(OFF_DP + 6 * k + 3, a.gd[k]); }
 #pragma unroll
-  for (int k = 0; k < S.qd; ++k) { fold(OFF_QD + 6 * k, a.fq[k]); fold_g(OFF_QD + 6 * k + 3, a.gq[k]); }
+  for (int k = 0; k < S.qd; ++k) { fold_mp(OFF_QD + 6 * k, a.fq[k]); fold_g(OFF_QD + 6 * k + 3, a.gq[k]); }
 }
 
 }  // namespace ms2
