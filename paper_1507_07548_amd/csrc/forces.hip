@@ -272,15 +272,16 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
 //     diagonal (each wave 16 of them); a wave scan of their counts gives
 //     each diagonal's offset in the diagonal-major list of accepted pairs.
 //  2. the list is processed 64 entries at a time, one pair per lane, the
-//     chunks dealt to the waves in turn.  For each diagonal of a chunk (a
-//     scalar walk over the offsets finds them), lane m holds row m's entry
-//     index: the diagonal's offset plus the count of set bits below bit m
-//     (mbcnt).  Lanes write their (row, diagonal) to those slots of a
-//     per-wave list, from which each lane reads its pair.
+//     chunks dealt to the waves in turn.  A chunk's diagonals follow from
+//     two ballots over the offsets.  For each of them lane m holds row m's
+//     entry index: the diagonal's offset plus the count of set bits below
+//     bit m (mbcnt).  Lanes write their (row, diagonal) to those slots of a
+//     per-wave list, from which each lane reads its pair, and keep the
+//     entry indices of the chunk's first diagonals for step 3.
 //  3. each lane stages its pair's force and torques in its wave's LDS area.
 //     Lane m then gathers the entries of molecule m of tile I (as a row, at
 //     its own entry index) and of tile J (as a column, at the index held by
-//     lane m - d): on each diagonal d of the chunk there is at most one of
+//     row m - d): on each diagonal d of the chunk there is at most one of
 //     each.  Sums stay in registers; there are no read-modify-writes of
 //     shared memory.
 //  4. the reaction on j follows from the pair's force and torque on i:
@@ -294,6 +295,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
 // fixed-order reduction over p is unchanged.
 // ---------------------------------------------------------------------------
 constexpr int kSymWaves = 4;
+constexpr int kKeepDiags = 6;   // diagonals per chunk whose entry indices are kept for the gather
 
 // Index in the chunk [q, q + 64) of this lane's row on a diagonal with word
 // wd starting at offset o - q (all wave-uniform), or -1 if the row is not on
@@ -324,6 +326,7 @@ struct SymTiles {
   double com[2][3][64];                 // [rows, columns][xyz][molecule]
   Real site[2][NR][64];
   Real stage[kSymWaves][9][64];         // F_i, tau_i, tau_j of each lane's pair
+  int er[kSymWaves][kKeepDiags][64];    // row m's entry index on the chunk's k-th diagonal, or -1
   Real kin[HF ? 2 : 1][6][HF ? 64 : 1]; // heat flux: lab v and w of rows, columns
 };
 
@@ -473,19 +476,19 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
   int a_np = 0, a_ns = 0;
   Real g_row[6] = {0, 0, 0, 0, 0, 0}, g_col[6] = {0, 0, 0, 0, 0, 0};
   Real(*stage)[TJ] = u.t.stage[wv];
-  int dfirst = 0;                            // wave-uniform
   int* list = s_list[wv];
+  int(*keep)[TJ] = u.t.er[wv];
   for (int q = wv * TJ; q < total; q += NW * TJ) {
     const bool valid = q + lane < total;
     const int qend = min(q + TJ, total);
-    // the chunk's diagonals: from the one holding entry q to the last one
-    // starting before the chunk's end (wave-uniform)
-    while (dfirst < TJ - 1 && __builtin_amdgcn_readlane(doff, dfirst + 1) <= q) ++dfirst;
-    int dlast = dfirst;
-    while (dlast < TJ - 1 && __builtin_amdgcn_readlane(doff, dlast + 1) < qend) ++dlast;
+    // the chunk's diagonals (wave-uniform): from the first one ending after
+    // q (it holds entry q) to the last one starting before the chunk's end
+    const int dfirst = min((int)__popcll(__builtin_amdgcn_ballot_w64(incl <= q)), TJ - 1);
+    const int dlast = (int)__popcll(__builtin_amdgcn_ballot_w64(doff < qend)) - 1;
     for (int dd = dfirst; dd <= dlast; ++dd) {
       const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
       if (er >= 0) list[er] = lane | (dd << 6);
+      if (dd - dfirst < kKeepDiags) keep[dd - dfirst][lane] = er;
     }
     wave_sync_lds();
     const int pr = list[lane];
@@ -555,8 +558,14 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     // gather: molecule `lane` of tile I at its own entry index; molecule
     // `lane` of tile J is the column of row lane - dd
     for (int dd = dfirst; dd <= dlast; ++dd) {
-      const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
-      const int ec = __shfl(er, (lane - dd) & (TJ - 1), TJ);
+      int er, ec;
+      if (dd - dfirst < kKeepDiags) {
+        er = keep[dd - dfirst][lane];
+        ec = keep[dd - dfirst][(lane - dd) & (TJ - 1)];
+      } else {
+        er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
+        ec = __shfl(er, (lane - dd) & (TJ - 1), TJ);
+      }
       if (er >= 0) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) g_row[c] += stage[c][er];
