@@ -326,7 +326,7 @@ struct SymTiles {
   double com[2][3][64];                 // [rows, columns][xyz][molecule]
   Real site[2][NR][64];
   Real stage[kSymWaves][9][64];         // F_i, tau_i, tau_j of each lane's pair
-  int er[kSymWaves][kKeepDiags][64];    // row m's entry index on the chunk's k-th diagonal, or -1
+  signed char er[kSymWaves][kKeepDiags][64];  // row m's entry index on the chunk's k-th diagonal, or -1
   Real kin[HF ? 2 : 1][6][HF ? 64 : 1]; // heat flux: lab v and w of rows, columns
 };
 
@@ -336,8 +336,16 @@ struct SymFinal {
   double sums[kSymWaves][kNumBlockSums];
 };
 
+// Waves per SIMD the register allocation must allow: six for the FP32
+// two-centre quadrupole kernel of the centre cut-off (it fits 80 registers
+// without spilling, and the kernel hides its LDS latency better with six
+// waves than with five); the compiler's choice otherwise.
 template <typename Real, int C, bool HF, bool SITE>
-__global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem* __restrict__ items,
+constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6 : 1;
+
+template <typename Real, int C, bool HF, bool SITE>
+__global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(kSymOccupancy<Real, C, HF, SITE>)))
+void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   int item_base,
                                                                   const SlotDev* __restrict__ slots,
                                                                   const SysParams* __restrict__ prm,
@@ -477,7 +485,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
   Real g_row[6] = {0, 0, 0, 0, 0, 0}, g_col[6] = {0, 0, 0, 0, 0, 0};
   Real(*stage)[TJ] = u.t.stage[wv];
   int* list = s_list[wv];
-  int(*keep)[TJ] = u.t.er[wv];
+  signed char(*keep)[TJ] = u.t.er[wv];
   for (int q = wv * TJ; q < total; q += NW * TJ) {
     const bool valid = q + lane < total;
     const int qend = min(q + TJ, total);
@@ -488,7 +496,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void pair_sym_kernel(const WorkItem
     for (int dd = dfirst; dd <= dlast; ++dd) {
       const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
       if (er >= 0) list[er] = lane | (dd << 6);
-      if (dd - dfirst < kKeepDiags) keep[dd - dfirst][lane] = er;
+      if (dd - dfirst < kKeepDiags) keep[dd - dfirst][lane] = (signed char)er;
     }
     wave_sync_lds();
     const int pr = list[lane];
