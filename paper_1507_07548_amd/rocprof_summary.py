@@ -4,6 +4,9 @@
       per-kernel calls, average and total duration from a --kernel-trace
       results database; with a substring, also the average duration of that
       kernel's largest-grid (batched) launches.
+  counters <counters.csv> <kernel substring>
+      every counter of a --pmc run per launch, averaged over the
+      largest-grid dispatches whose name holds the substring.
   traffic <fetch.csv> <write.csv> <copy_bytes> <kernel substring>
       HBM bytes per launch of the largest-grid dispatches whose name holds
       the substring, from two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
@@ -84,6 +87,25 @@ def _copy_kib(disp):
     return max(copies)
 
 
+def counters(csv_path, substring):
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        if substring not in r["Kernel_Name"]:
+            continue
+        d = per.setdefault(r["Dispatch_Id"], [int(r["Grid_Size"]), r["Kernel_Name"].split("(")[0], {}])
+        d[2][r["Counter_Name"]] = d[2].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no dispatch of a kernel named like {substring!r}")
+    gmax = max(d[0] for d in per.values())
+    big = [d for d in per.values() if d[0] == gmax]
+    names = sorted(big[0][2])
+    lines = [f"Kernel `{big[0][1]}`: {len(big)} launches of grid {gmax} work-items.", "",
+             "| counter | per launch |", "|---|---|"]
+    for k in names:
+        lines.append(f"| {k} | {sum(d[2][k] for d in big) / len(big):.6g} |")
+    return "\n".join(lines)
+
+
 def traffic(fetch_csv, write_csv, copy_bytes, substring):
     fd, wd = _dispatches(fetch_csv, "FETCH_SIZE"), _dispatches(write_csv, "WRITE_SIZE")
     f_kib, nf, name = _per_launch(fd, substring)
@@ -106,7 +128,9 @@ def traffic(fetch_csv, write_csv, copy_bytes, substring):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 2 and sys.argv[1] == "traffic":
+    if len(sys.argv) >= 2 and sys.argv[1] == "counters":
+        print(counters(sys.argv[2], sys.argv[3]))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5]))
     elif len(sys.argv) >= 2 and sys.argv[1] == "kernels":
         print(summarize(sys.argv[2]))
