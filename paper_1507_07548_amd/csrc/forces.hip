@@ -634,37 +634,48 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
 
 // ---------------------------------------------------------------------------
 // Fixed-order reductions of the pair partials.
-//  reduce_force_kernel: one thread per molecule sums its j-range partials in
-//    order, in FP64 (the partials are in the slot's Real: each is a sum of at
-//    most one tile's pair terms); grid (molecule blocks, slots).  OVERWRITES
-//    force and torque.
+//  reduce_force_kernel: one thread per molecule and component sums its
+//    partials in order, in FP64 (the partials are in the slot's Real: each is
+//    a sum of at most one tile's pair terms); grid (6 x molecule blocks,
+//    slots).  OVERWRITES force and torque.
 //  reduce_sums_kernel: one block per slot; item sums (each thread a
 //    contiguous run, then a tree), species counts, Ewald constants and the LJ
 //    tail.  OVERWRITES sums.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __restrict__ slots) {
+  // one thread per (component, molecule): the grid's x holds six runs of
+  // molecule blocks, one per force/torque component, so that the largest
+  // systems' serial chains are one component long
   const SlotDev& sd = slots[blockIdx.y];
   if (!sd.active) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int mb = gridDim.x / 6, c = blockIdx.x / mb;
+  const int i = (blockIdx.x - c * mb) * 256 + threadIdx.x;
   if (i >= sd.n) return;
-  const int np = sd.npad, ld = sd.com_ld;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  if (sd.pf_single) {
-    const float* pf = reinterpret_cast<const float*>(sd.pf);
-    for (int p = 0; p < sd.jsplits; ++p)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] += (double)pf[((size_t)p * 6 + c) * np + i];
-  } else {
-    const double* pf = reinterpret_cast<const double*>(sd.pf);
-    for (int p = 0; p < sd.jsplits; ++p)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] += pf[((size_t)p * 6 + c) * np + i];
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    sd.force[c * ld + i] = v[c];
-    sd.torque[c * ld + i] = v[3 + c];
-  }
+  const int np = sd.npad, ld = sd.com_ld, nparts = sd.jsplits;
+  const size_t stride = (size_t)6 * np;
+  double v = 0.0;
+  // the loads of four partials are issued before their additions, which
+  // keep the order p = 0, 1, 2, ...
+  auto reduce = [&](auto* __restrict__ pf) {
+    int p = 0;
+    for (; p + 4 <= nparts; p += 4) {
+      const double x0 = (double)pf[(size_t)p * stride], x1 = (double)pf[(size_t)(p + 1) * stride];
+      const double x2 = (double)pf[(size_t)(p + 2) * stride], x3 = (double)pf[(size_t)(p + 3) * stride];
+      v += x0;
+      v += x1;
+      v += x2;
+      v += x3;
+    }
+    for (; p < nparts; ++p) v += (double)pf[(size_t)p * stride];
+  };
+  if (sd.pf_single)
+    reduce(reinterpret_cast<const float*>(sd.pf) + (size_t)c * np + i);
+  else
+    reduce(reinterpret_cast<const double*>(sd.pf) + (size_t)c * np + i);
+  if (c < 3)
+    sd.force[c * ld + i] = v;
+  else
+    sd.torque[(c - 3) * ld + i] = v;
 }
 
 __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restrict__ slots,
@@ -822,7 +833,7 @@ hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool s
 
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_force_kernel, dim3((max_n + 255) / 256, nslots), dim3(256), 0, st, slots);
+  hipLaunchKernelGGL(reduce_force_kernel, dim3(6 * ((max_n + 255) / 256), nslots), dim3(256), 0, st, slots);
   hipLaunchKernelGGL(reduce_sums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();
 }

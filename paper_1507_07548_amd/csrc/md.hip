@@ -233,38 +233,35 @@ __global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict
   if (i >= sd.n) return;
   const int np = sd.com_ld;
   if (m.integrator == MS2_GEAR) {
-    for (int c = 0; c < 3; ++c) {
-      double y0 = m.r[(0 * 3 + c) * np + i], y1 = m.r[(1 * 3 + c) * np + i],
-             y2 = m.r[(2 * 3 + c) * np + i], y3 = m.r[(3 * 3 + c) * np + i],
-             y4 = m.r[(4 * 3 + c) * np + i];
-      m.r[(0 * 3 + c) * np + i] = y0 + y1 + y2 + y3 + y4;
-      m.r[(1 * 3 + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
-      m.r[(2 * 3 + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
-      m.r[(3 * 3 + c) * np + i] = y3 + 4.0 * y4;
-    }
-    if (m.rotating) {
-      for (int c = 0; c < 3; ++c) {
-        double y0 = m.w[(0 * 3 + c) * np + i], y1 = m.w[(1 * 3 + c) * np + i],
-               y2 = m.w[(2 * 3 + c) * np + i], y3 = m.w[(3 * 3 + c) * np + i],
-               y4 = m.w[(4 * 3 + c) * np + i];
-        m.w[(0 * 3 + c) * np + i] = y0 + y1 + y2 + y3 + y4;
-        m.w[(1 * 3 + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
-        m.w[(2 * 3 + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
-        m.w[(3 * 3 + c) * np + i] = y3 + 4.0 * y4;
+    // the Gear arrays are distinct allocations: every load is issued before
+    // the stores (Pascal-triangle predictor on the 5 scaled derivatives of
+    // each of nc components)
+    auto predict = [&](double* __restrict__ y, int nc, double* y0_out) {
+      double a[5][4];
+      for (int d = 0; d < 5; ++d)
+        for (int c = 0; c < nc; ++c) a[d][c] = y[(d * nc + c) * np + i];
+      for (int c = 0; c < nc; ++c) {
+        const double y0 = a[0][c], y1 = a[1][c], y2 = a[2][c], y3 = a[3][c], y4 = a[4][c];
+        y0_out[c] = y0 + y1 + y2 + y3 + y4;
+        y[(1 * nc + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
+        y[(2 * nc + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
+        y[(3 * nc + c) * np + i] = y3 + 4.0 * y4;
       }
-      double q0[4];
-      for (int c = 0; c < 4; ++c) {
-        double y0 = m.q[(0 * 4 + c) * np + i], y1 = m.q[(1 * 4 + c) * np + i],
-               y2 = m.q[(2 * 4 + c) * np + i], y3 = m.q[(3 * 4 + c) * np + i],
-               y4 = m.q[(4 * 4 + c) * np + i];
-        q0[c] = y0 + y1 + y2 + y3 + y4;
-        m.q[(1 * 4 + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
-        m.q[(2 * 4 + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
-        m.q[(3 * 4 + c) * np + i] = y3 + 4.0 * y4;
-      }
+    };
+    double* const r = m.r;
+    double* const w = m.w;
+    double* const q = m.q;
+    const bool rotating = m.rotating;
+    double p0[4];
+    predict(r, 3, p0);
+    for (int c = 0; c < 3; ++c) r[c * np + i] = p0[c];
+    if (rotating) {
+      predict(w, 3, p0);
+      for (int c = 0; c < 3; ++c) w[c * np + i] = p0[c];
+      predict(q, 4, p0);
       // the force evaluation uses the predicted orientation projected onto |q| = 1
-      const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
-      for (int c = 0; c < 4; ++c) m.q[c * np + i] = q0[c] / nq;
+      const double nq = sqrt(p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2] + p0[3] * p0[3]);
+      for (int c = 0; c < 4; ++c) q[c * np + i] = p0[c] / nq;
     }
   } else {
     const double h = 0.5 * m.dt / tab->sp[clamp_species(sd.species[i], tab->nsp)].mass;
@@ -318,62 +315,72 @@ __global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDe
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += kMdThreads) {
-    const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
-    if (m.integrator == MS2_GEAR) {
-      for (int c = 0; c < 3; ++c) {
-        const double delta = 0.5 * dt * dt * sd.force[c * ld + i] / D.mass - m.r[(2 * 3 + c) * np + i];
-        for (int d = 0; d < 5; ++d) m.r[(d * 3 + c) * np + i] += ct[d] * delta;
-      }
-      if (m.rotating) {
-        double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
-        for (int c = 0; c < 4; ++c) q[c] = m.q[c * np + i];
+  // corrector (the state arrays are distinct allocations: each loop is a
+  // function of restrict pointers, so loads may pass stores)
+  auto correct = [&](double* __restrict__ gr, double* __restrict__ gw, double* __restrict__ gq,
+                     double* __restrict__ gv, const double* __restrict__ gf, const double* __restrict__ gt) {
+    for (int i = tid; i < n; i += kMdThreads) {
+      const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
+      if (m.integrator == MS2_GEAR) {
         for (int c = 0; c < 3; ++c) {
-          w[c] = m.w[c * np + i];
-          tq[c] = sd.torque[c * ld + i];
+          const double delta = 0.5 * dt * dt * gf[c * ld + i] / D.mass - gr[(2 * 3 + c) * np + i];
+          for (int d = 0; d < 5; ++d) gr[(d * 3 + c) * np + i] += ct[d] * delta;
         }
-        qrot(q[0], q[1], q[2], q[3], A);
-        body_torque(A, tq, tb);
-        euler_rate(D.inertia, tb, w, wd);
-        quat_rate(q, w, qd);
+        if (m.rotating) {
+          double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
+          for (int c = 0; c < 4; ++c) q[c] = gq[c * np + i];
+          for (int c = 0; c < 3; ++c) {
+            w[c] = gw[c * np + i];
+            tq[c] = gt[c * ld + i];
+          }
+          qrot(q[0], q[1], q[2], q[3], A);
+          body_torque(A, tq, tb);
+          euler_rate(D.inertia, tb, w, wd);
+          quat_rate(q, w, qd);
+          for (int c = 0; c < 3; ++c) {
+            const double delta = dt * wd[c] - gw[(1 * 3 + c) * np + i];
+            for (int d = 0; d < 5; ++d) gw[(d * 3 + c) * np + i] += cr[d] * delta;
+          }
+          double q0[4];
+          for (int c = 0; c < 4; ++c) {
+            const double delta = dt * qd[c] - gq[(1 * 4 + c) * np + i];
+            for (int d = 0; d < 5; ++d) gq[(d * 4 + c) * np + i] += cr[d] * delta;
+            q0[c] = gq[c * np + i];
+          }
+          const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+          for (int c = 0; c < 4; ++c) gq[c * np + i] = q0[c] / nq;
+        }
         for (int c = 0; c < 3; ++c) {
-          const double delta = dt * wd[c] - m.w[(1 * 3 + c) * np + i];
-          for (int d = 0; d < 5; ++d) m.w[(d * 3 + c) * np + i] += cr[d] * delta;
+          gr[c * np + i] = wrap(gr[c * np + i], P.L, P.invL);
+          gv[c * np + i] = gr[(1 * 3 + c) * np + i] / dt;
         }
-        double q0[4];
-        for (int c = 0; c < 4; ++c) {
-          const double delta = dt * qd[c] - m.q[(1 * 4 + c) * np + i];
-          for (int d = 0; d < 5; ++d) m.q[(d * 4 + c) * np + i] += cr[d] * delta;
-          q0[c] = m.q[c * np + i];
-        }
-        const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
-        for (int c = 0; c < 4; ++c) m.q[c * np + i] = q0[c] / nq;
+      } else {
+        const double h = 0.5 * dt / D.mass;
+        for (int c = 0; c < 3; ++c) gv[c * np + i] += h * gf[c * ld + i];
       }
-      for (int c = 0; c < 3; ++c) {
-        m.r[c * np + i] = wrap(m.r[c * np + i], P.L, P.invL);
-        v[c * np + i] = m.r[(1 * 3 + c) * np + i] / dt;
-      }
-    } else {
-      const double h = 0.5 * dt / D.mass;
-      for (int c = 0; c < 3; ++c) v[c * np + i] += h * sd.force[c * ld + i];
     }
-  }
+  };
+  correct(m.r, m.w, m.q, v, sd.force, sd.torque);
   __syncthreads();
   double k2, kr2;
   kinetic(m, tab, sd, v, np, red, k2, kr2);
   if (m.temperature > 0.0) {
     const double ft = sqrt(m.temperature * m.f_tr / k2);
     const double fr = (m.f_rot > 0.0 && kr2 > 0.0) ? sqrt(m.temperature * m.f_rot / kr2) : 1.0;
-    for (int i = tid; i < n; i += kMdThreads) {
-      for (int c = 0; c < 3; ++c) {
-        v[c * np + i] *= ft;
-        if (m.integrator == MS2_GEAR) m.r[(1 * 3 + c) * np + i] *= ft;
+    auto rescale = [&](double* __restrict__ gr, double* __restrict__ gw, double* __restrict__ gq,
+                       double* __restrict__ gv) {
+      for (int i = tid; i < n; i += kMdThreads) {
+        for (int c = 0; c < 3; ++c) {
+          gv[c * np + i] *= ft;
+          if (m.integrator == MS2_GEAR) gr[(1 * 3 + c) * np + i] *= ft;
+        }
+        if (m.rotating && fr != 1.0) {
+          for (int c = 0; c < 3; ++c) gw[c * np + i] *= fr;
+          for (int c = 0; c < 4; ++c) gq[(1 * 4 + c) * np + i] *= fr;
+        }
       }
-      if (m.rotating && fr != 1.0) {
-        for (int c = 0; c < 3; ++c) m.w[c * np + i] *= fr;
-        for (int c = 0; c < 4; ++c) m.q[(1 * 4 + c) * np + i] *= fr;
-      }
-    }
+    };
+    rescale(m.r, m.w, m.q, v);
     k2 *= ft * ft;
     kr2 *= fr * fr;
     __syncthreads();
