@@ -275,3 +275,44 @@ def test_autotuner_picks_a_valid_shape_for_every_bucket():
             assert (w == 0 and j == 64) or (w in (1, 4) and j % (64 * w) == 0)
     f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, ctx=ctx, label="after autotune")
     assert ef < 1e-5
+
+
+# --------------------------------------------------------------------------
+# centres outside [0, L) and on the box faces: the symmetric kernel's cut-off
+# bits use min(|d|, L - |d|) when every centre of an item lies in [0, L] and
+# the rint form otherwise; both must give the oracle's pairs exactly
+# --------------------------------------------------------------------------
+def symmetric_ctx(s, prec):
+    ctx = ms2.Context(s.species)
+    ctx.set_tile_config(s.n, prec, 0, 64, mode=0)
+    return ctx
+
+
+@pytest.mark.parametrize("prec", [ms2.FP64, ms2.FP32])
+def test_unwrapped_centres_match_the_oracle(prec):
+    s = I.jittered(I.quadrupolar_fluid(n=300, density=0.6), 0.1, seed=21)
+    rng = np.random.default_rng(22)
+    # a third of the molecules moved by whole box lengths (-2..2 per
+    # component): items mixing moved and unmoved centres take the rint form
+    moved = rng.random(s.n) < 1 / 3
+    k = rng.integers(-2, 3, size=(s.n, 3)) * moved[:, None]
+    s.com = s.com + k * s.params.box
+    assert (s.com < 0).any() and (s.com > s.params.box).any()
+    f, t, su, fo, to, so, ef, et = compare(s, prec, ctx=symmetric_ctx(s, prec), label="unwrapped centres")
+    tol = 1e-11 if prec == ms2.FP64 else 1e-5
+    assert ef < tol and et < tol, (ef, et)
+    check_sums(su, so, 1e-11 if prec == ms2.FP64 else 1e-6, 1e-12 if prec == ms2.FP64 else 1e-8)
+
+
+def test_centres_on_the_box_faces():
+    s = I.jittered(I.quadrupolar_fluid(n=300, density=0.6), 0.1, seed=23)
+    L = s.params.box
+    rng = np.random.default_rng(24)
+    idx = rng.choice(s.n, size=40, replace=False)
+    # exactly 0 or exactly L in one component: inside [0, L], so the image-free
+    # form applies; a pair across the faces differs by exactly L there
+    for m, i in enumerate(idx):
+        s.com[i, m % 3] = 0.0 if m % 2 == 0 else L
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, ctx=symmetric_ctx(s, ms2.FP64), label="centres on faces")
+    assert ef < 1e-11 and et < 1e-11, (ef, et)
+    check_sums(su, so, 1e-11, 1e-12)
