@@ -599,36 +599,36 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     u.f.part[wv][6 + c][lane] = g_col[c];
   }
   __syncthreads();
-  if (wv == 0) {
-    double fr[6], fc[6];
+  // wave w writes three of the twelve components (rows 0-2, rows 3-5,
+  // columns 0-2, columns 3-5), each summed over the waves in wave order; on
+  // the diagonal item the columns are the rows and waves 0/1 add both
+  {
+    const bool col_side = wv >= 2;
+    const int c0 = 3 * (wv & 1);
+    Real* pf = reinterpret_cast<Real*>(sd.pf);
+    if (!(diag && col_side) && lane < (col_side ? ncol : nrow)) {
+      Real* out = pf + (size_t)(col_side ? it.part_j : it.part) * 6 * np + (col_side ? it.j0 : it.i0) + lane;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      fr[c] = (double)u.f.part[0][c][lane];
-      fc[c] = (double)u.f.part[0][6 + c][lane];
-    }
+      for (int k = 0; k < 3; ++k) {
+        const int c = c0 + k, src = col_side ? 6 + c : c;
+        double t = (double)u.f.part[0][src][lane];
 #pragma unroll
-    for (int w = 1; w < NW; ++w)
+        for (int w = 1; w < NW; ++w) t += (double)u.f.part[w][src][lane];
+        if (diag) {
+          double tc = (double)u.f.part[0][6 + c][lane];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        fr[c] += (double)u.f.part[w][c][lane];
-        fc[c] += (double)u.f.part[w][6 + c][lane];
+          for (int w = 1; w < NW; ++w) tc += (double)u.f.part[w][6 + c][lane];
+          t += tc;
+        }
+        out[(size_t)c * np] = (Real)t;
       }
-    Real* pf_i = reinterpret_cast<Real*>(sd.pf) + (size_t)it.part * 6 * np;
-    if (diag) {
-      if (lane < nrow)
-        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = (Real)(fr[c] + fc[c]);
-    } else {
-      Real* pf_j = reinterpret_cast<Real*>(sd.pf) + (size_t)it.part_j * 6 * np;
-      if (lane < nrow)
-        for (int c = 0; c < 6; ++c) pf_i[c * np + it.i0 + lane] = (Real)fr[c];
-      if (lane < ncol)
-        for (int c = 0; c < 6; ++c) pf_j[c * np + it.j0 + lane] = (Real)fc[c];
     }
-  } else if (wv == 1 && lane < kNumBlockSums) {
-    double t = u.f.sums[0][lane];
+    if (wv == 3 && lane < kNumBlockSums) {
+      double t = u.f.sums[0][lane];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) t += u.f.sums[w][lane];
-    sd.bsum[(size_t)it.local * kNumBlockSums + lane] = t;
+      for (int w = 1; w < NW; ++w) t += u.f.sums[w][lane];
+      sd.bsum[(size_t)it.local * kNumBlockSums + lane] = t;
+    }
   }
 }
 
