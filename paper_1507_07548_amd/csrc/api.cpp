@@ -320,9 +320,9 @@ TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
   if (mode == 0) {  // one system per launch: many small items to spread one system
     c.waves = 1;
     c.jchunk = 64 * std::max(1, (n + 1023) / 1024);
-  } else {          // batched: larger tiles, fewer partials
-    c.waves = ctx->cls <= 3 ? 4 : 1;
-    c.jchunk = c.waves == 4 ? 1024 : 256;
+  } else {          // batched: symmetric tile pairs, every pair evaluated once
+    c.waves = 0;
+    c.jchunk = 64;
   }
   return c;
 }

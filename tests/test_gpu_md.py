@@ -136,9 +136,11 @@ def test_alone_and_in_a_mix_are_bitwise_identical(symmetric):
               for n, rho in [(1500, 0.4), (520, 0.75), (3000, 0.3)]]
     say(f"[gpu] alone vs mix, fp32, graph, symmetric={symmetric}")
     ctx = ms2.Context(a.species)
-    if symmetric:
-        for n in (520, 700, 1500, 3000):
+    for n in (520, 700, 1500, 3000):
+        if symmetric:
             ctx.set_tile_config(n, ms2.FP32, 0, 64, mode=1)
+        else:   # row-owned items of four waves
+            ctx.set_tile_config(n, ms2.FP32, 4, 1024, mode=1)
     alone = ms2.Batch(ctx, 1)
     sa = alone.admit(a, ms2.FP32)
     alone.step(30)
