@@ -169,8 +169,8 @@ def main():
                     help="first copy this many MiB device to device (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs each system on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py measures one GPU only: every system runs on a single MI355X and "
+              "sharding systems across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
