@@ -299,3 +299,33 @@ def test_site_cut_heat_flux_acf_fp64():
     np.testing.assert_array_equal(g["acf_q_cnt"], o["acf_q_cnt"])
     assert o["acf_q"][0] > 0
     np.testing.assert_allclose(g["acf_q"], o["acf_q"], rtol=0, atol=1e-9 * o["acf_q"][0])
+
+
+def test_site_cut_ewald_water_ions_md_fp64():
+    s = I.ionic_solution(n_steps=10, rdf_every=0)
+    s = site_mode(s, rc=0.45 * s.params.box)
+    say("[gpu] site-site cut-off, water + ions Gear NVT with Ewald, 10 steps fp64")
+    o = oracle.md(s)
+    (g,) = md_run([s], ms2.FP64, 10)
+    st = o["state"]
+    L = s.params.box
+    dc = np.abs((g["com"] - st.com) - L * np.rint((g["com"] - st.com) / L)).max()
+    dv = np.abs(g["vel"] - st.vel).max() / np.abs(st.vel).max()
+    say(f"  max|dcom| {dc:.2e}  max|dv|/max|v| {dv:.2e}")
+    assert dc < 1e-8 and dv < 1e-8
+
+
+def test_site_cut_fp32_trajectory_tracks_oracle():
+    # FP32 rounding of the trajectory stays near 1e-7; an LJ site pair that
+    # crosses rc on one side only (FP32 decision) moves one molecule's
+    # velocity by ~|u'(rc)| dt / m = 4e-5 (reduced units), whence the bounds
+    s = site_mode(I.quadrupolar_fluid(n=256, density=0.6, n_steps=20, sample_every=1), rc=3.3)
+    say("[gpu] site-site cut-off, 2CLJQ Gear NVT 20 steps fp32")
+    o = oracle.md(s)
+    (g,) = md_run([s], ms2.FP32, 20)
+    st = o["state"]
+    L = s.params.box
+    dc = np.abs((g["com"] - st.com) - L * np.rint((g["com"] - st.com) / L)).max()
+    dv = np.abs(g["vel"] - st.vel).max() / np.abs(st.vel).max()
+    say(f"  max|dcom| {dc:.2e}  max|dv|/max|v| {dv:.2e}")
+    assert dc < 1e-5 and dv < 1e-4
