@@ -13,7 +13,8 @@ corrector, isokinetic thermostat, Lustig moment sums):
 
 Printed JSON line: site-pair interactions/s of the batched form (value), MD
 steps/s, the plain one-system-per-launch form on a sample of the same
-systems, the pair kernel's roofline (HIP events around its launches inside
+systems, the same batched workload in FP64, a serving trace (p50/p99
+latency), the pair kernel's roofline (HIP events around its launches inside
 the timed graph) and the oracle timed on the host as a CPU baseline.
 """
 import argparse
@@ -147,6 +148,27 @@ def plain_form(ms2, torch, ctx, sample, K, W):
             "form": "one system per launch, no graph, plain tile shapes"}
 
 
+def precision_form(ms2, torch, ctx, systems, K, W, graph):
+    """The same batched workload with FP64 site arithmetic (symmetric tile
+    pairs, the default shape of batched launches)."""
+    log(f"[bench] FP64 form on {len(systems)} systems")
+    b = ms2.Batch(ctx, len(systems))
+    slots = [b.admit(s, ms2.FP64) for s in systems]
+    b.step(W if W > 0 else 1, graph=graph)
+    torch.cuda.synchronize()
+    pb = [b.sample(s, state=False) for s in slots]
+    t0 = time.perf_counter()
+    b.step(K, graph=graph)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pa = [b.sample(s, state=False) for s in slots]
+    assert all(a["status"] == 0 for a in pa)
+    sp = sum(a["site_pairs_total"] - p["site_pairs_total"] for a, p in zip(pa, pb))
+    b.close()
+    return {"value": sp / (t1 - t0), "ms_per_step": (t1 - t0) / K * 1e3, "systems": len(systems),
+            "form": "FP64 site arithmetic and sums, same systems, symmetric tile pairs, graph"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +179,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form of the batched workload")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=400)
     ap.add_argument("--no-graph", action="store_true",
@@ -240,6 +263,7 @@ def main():
 
     sample = systems[: args.plain_sample]
     plain = plain_form(ms2, torch, ctx, sample, K, W) if sample else None
+    fp64 = None if args.no_fp64 else precision_form(ms2, torch, ctx, systems, K, W, graph)
     serving = None if args.no_serve else serve_trace(args.serve_requests, args.serve_steps)
 
     line = {
@@ -273,6 +297,8 @@ def main():
     if plain is not None:
         line["plain"] = plain
         line["batched_over_plain"] = value / plain["value"]
+    if fp64 is not None:
+        line["fp64"] = fp64
     if serving is not None:
         line["serving"] = serving
     if not args.no_cpu_baseline:
