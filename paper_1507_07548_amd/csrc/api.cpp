@@ -20,8 +20,8 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, const WorkItem* items,
-                       int base, int count, const SlotDev* slots, const SysParams* prm,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+                       const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st);
@@ -561,7 +561,7 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
   const ms2::CachedItems& ci = ctx->item_cache[std::make_tuple(n_mol, cfg.waves, cfg.jchunk)];
   MS2_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n_mol, st));
   MS2_HIP(launch_pair(ctx->cls, h_params->precision, cfg.waves, false, h_params->cutoff_mode == MS2_CUT_SITE,
-                      (const WorkItem*)ci.buf.p, 0, nitems,
+                      ctx->tab.nsp == 1, (const WorkItem*)ci.buf.p, 0, nitems,
                       r->d_slot, r->d_prm, ctx->d_tab, st));
   MS2_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, n_mol, st));
   MS2_HIP(hipEventRecord(r->ev, st));

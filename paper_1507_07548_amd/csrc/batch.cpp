@@ -23,8 +23,8 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, const WorkItem* items,
-                       int base, int count, const SlotDev* slots, const SysParams* prm,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+                       const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st);
@@ -347,8 +347,8 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
   }
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_begin[timed_step], st));
   for (auto& g : b->groups)
-    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, di, g.begin, g.end - g.begin, ds,
-                        dp, ctx->d_tab, st));
+    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, ctx->tab.nsp == 1, di, g.begin,
+                        g.end - g.begin, ds, dp, ctx->d_tab, st));
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
   MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
   if (b->any_ewald)

@@ -343,7 +343,9 @@ struct SymFinal {
 template <typename Real, int C, bool HF, bool SITE>
 constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6 : 1;
 
-template <typename Real, int C, bool HF, bool SITE>
+// ONE: every molecule of the system is species 0 (instantiated for classes
+// 0-3); the species reads and table indexing drop out.
+template <typename Real, int C, bool HF, bool SITE, bool ONE>
 __global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(kSymOccupancy<Real, C, HF, SITE>)))
 void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   int item_base,
@@ -503,7 +505,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     const int row = pr & (TJ - 1);
     const int col = (row + (pr >> 6)) & (TJ - 1);
 
-    const int spi = s_sp[0][row], spj = s_sp[1][col];
+    const int spi = ONE ? 0 : s_sp[0][row], spj = ONE ? 0 : s_sp[1][col];
     double dx, dy, dz, r2d;
     min_image(u.t.com[0][0][row], u.t.com[0][1][row], u.t.com[0][2][row], u.t.com[1][0][col],
               u.t.com[1][1][col], u.t.com[1][2][col], L, invL, dx, dy, dz, r2d);
@@ -518,8 +520,8 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     ai.zero();
     const bool elec_in = !SITE || r2d < rc2;
     int nlj_in = 0;
-    eval_molecule_pair<Real, C, false, TJ, SITE>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry, Rz,
-                                                 R2, ai, unused, acc, (Real)rc2, elec_in, &nlj_in);
+    eval_molecule_pair<Real, C, false, TJ, SITE, ONE>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry,
+                                                      Rz, R2, ai, unused, acc, (Real)rc2, elec_in, &nlj_in);
     // interacting site pairs; in the site-site mode a listed pair counts
     // only when at least one of its site pairs interacts
     int ns = s_tab.nsite[spi][spj];
@@ -784,24 +786,32 @@ static hipError_t launch_pair_cw(const WorkItem* items, int base, int count, con
 }
 
 template <typename Real, int C, bool HF, bool SITE>
-static hipError_t launch_pair_sym(const WorkItem* items, int base, int count, const SlotDev* slots,
-                                  const SysParams* prm, const SpeciesTable* tab, hipStream_t st) {
-  hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE>), dim3(count), dim3(64 * kSymWaves), 0, st, items,
-                     base, slots, prm, tab);
+static hipError_t launch_pair_sym(bool one_species, const WorkItem* items, int base, int count,
+                                  const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
+                                  hipStream_t st) {
+  if constexpr (C <= 3) {
+    if (one_species) {
+      hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE, true>), dim3(count), dim3(64 * kSymWaves), 0, st,
+                         items, base, slots, prm, tab);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE, false>), dim3(count), dim3(64 * kSymWaves), 0, st,
+                     items, base, slots, prm, tab);
   return hipGetLastError();
 }
 
 template <typename Real, int C>
-static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, const WorkItem* items, int base,
-                                int count, const SlotDev* slots, const SysParams* prm,
+static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, bool one_species, const WorkItem* items,
+                                int base, int count, const SlotDev* slots, const SysParams* prm,
                                 const SpeciesTable* tab, hipStream_t st) {
   if (waves == 0) {  // symmetric tile pairs
     if (count <= 0) return hipSuccess;
     if (site_cut)
-      return heat_flux ? launch_pair_sym<Real, C, true, true>(items, base, count, slots, prm, tab, st)
-                       : launch_pair_sym<Real, C, false, true>(items, base, count, slots, prm, tab, st);
-    return heat_flux ? launch_pair_sym<Real, C, true, false>(items, base, count, slots, prm, tab, st)
-                     : launch_pair_sym<Real, C, false, false>(items, base, count, slots, prm, tab, st);
+      return heat_flux ? launch_pair_sym<Real, C, true, true>(one_species, items, base, count, slots, prm, tab, st)
+                       : launch_pair_sym<Real, C, false, true>(one_species, items, base, count, slots, prm, tab, st);
+    return heat_flux ? launch_pair_sym<Real, C, true, false>(one_species, items, base, count, slots, prm, tab, st)
+                     : launch_pair_sym<Real, C, false, false>(one_species, items, base, count, slots, prm, tab, st);
   }
   // the heat flux and the site-site cut-off run on symmetric items only
   if (heat_flux || site_cut) return hipErrorInvalidValue;
@@ -811,14 +821,14 @@ static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, const 
   return launch_pair_cw<Real, C, 1>(items, base, count, slots, prm, tab, st);
 }
 
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, const WorkItem* items,
-                       int base, int count, const SlotDev* slots, const SysParams* prm,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+                       const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st) {
 #define MS2_PAIR_CASE(C)                                                                                       \
   case C:                                                                                                      \
     return precision == MS2_FP32                                                                               \
-               ? launch_pair_c<float, C>(waves, heat_flux, site_cut, items, base, count, slots, prm, tab, st)  \
-               : launch_pair_c<double, C>(waves, heat_flux, site_cut, items, base, count, slots, prm, tab, st);
+               ? launch_pair_c<float, C>(waves, heat_flux, site_cut, one_species, items, base, count, slots, prm, tab, st)  \
+               : launch_pair_c<double, C>(waves, heat_flux, site_cut, one_species, items, base, count, slots, prm, tab, st);
   switch (cls) {
     MS2_PAIR_CASE(0)
     MS2_PAIR_CASE(1)

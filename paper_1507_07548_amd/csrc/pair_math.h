@@ -311,11 +311,13 @@ struct ElecParams {
 // i's sites go to ai; with JSIDE those on j's sites go to aj (force on a j
 // site is minus the force on its partner).  acc collects the pair's energy,
 // total force on i and d2U/ds2.
+// ONE: the system has one species (spi = spj = 0); its site counts are then
+// wave-uniform and the site loops branch on scalars.
 // SITE: the site-site cut-off mode.  An LJ site pair then interacts only
 // when its own squared distance is below lj_rc2 (and adds one to *nlj_in),
 // and the electrostatic site pairs only when elec_in (the centres inside the
 // cut-off).  Without SITE every site pair of the molecule pair interacts.
-template <typename Real, int C, bool JSIDE, int STRIDE, bool SITE = false>
+template <typename Real, int C, bool JSIDE, int STRIDE, bool SITE = false, bool ONE = false>
 __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* sj, int spi, int spj,
                                                    const PairTables<Real, C>& T,
                                                    const ElecParams<Real>& E, Real Rx, Real Ry,
@@ -327,8 +329,11 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
   constexpr int NLJ = SiteAcc<Real, C>::NLJ;
   constexpr int OFF_CH = 3 * S.lj, OFF_DP = OFF_CH + 3 * S.ch, OFF_QD = OFF_DP + 6 * S.dp;
   constexpr bool CENTRAL = S.central != 0;
-  const int nlj_i = T.cnt[spi][0], nch_i = T.cnt[spi][1], ndp_i = T.cnt[spi][2], nqd_i = T.cnt[spi][3];
-  const int nlj_j = T.cnt[spj][0], nch_j = T.cnt[spj][1], ndp_j = T.cnt[spj][2], nqd_j = T.cnt[spj][3];
+  auto count = [&](int sp, int k) {
+    return ONE ? __builtin_amdgcn_readfirstlane(T.cnt[0][k]) : T.cnt[sp][k];
+  };
+  const int nlj_i = count(spi, 0), nch_i = count(spi, 1), ndp_i = count(spi, 2), nqd_i = count(spi, 3);
+  const int nlj_j = count(spj, 0), nch_j = count(spj, 1), ndp_j = count(spj, 2), nqd_j = count(spj, 3);
   auto J = [&](int k) { return sj[k * STRIDE]; };
 
   // Lennard-Jones site pairs
