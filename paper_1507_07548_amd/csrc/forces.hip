@@ -162,7 +162,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
   const SysParams& P = prm[it.slot];
   const int tid = threadIdx.x;
   const int nsp = P.nsp;
-  s_tab.load(tab, P, tid, TJ);
+  s_tab.load(tab, P, P.nsp, tid, TJ);
 
   const int n = sd.n, ld = sd.com_ld, np = sd.npad;
   const double L = P.L, invL = P.invL, rc2 = P.rc2;
@@ -323,10 +323,13 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 template <typename Real, int NR, bool HF>
 struct SymTiles {
-  double com[2][3][64];                 // [rows, columns][xyz][molecule]
+  // centres [xyz][molecule] of the columns, then the rows: phase 1 reads
+  // three columns' components at offsets of one base address
+  double comj[3][64];
+  double comi[3][64];
   Real site[2][NR][64];
   Real stage[kSymWaves][9][64];         // F_i, tau_i, tau_j of each lane's pair
-  signed char er[kSymWaves][kKeepDiags][64];  // row m's entry index on the chunk's k-th diagonal, or -1
+  unsigned char er[kSymWaves][kKeepDiags][64];  // row m's entry index on the chunk's k-th diagonal, or 255
   Real kin[HF ? 2 : 1][6][HF ? 64 : 1]; // heat flux: lab v and w of rows, columns
 };
 
@@ -374,7 +377,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   // the walks over diagonals run on scalar registers
   const int tid = threadIdx.x, lane = tid & (TJ - 1), wv = __builtin_amdgcn_readfirstlane(tid / TJ);
   const int nsp = P.nsp;
-  s_tab.load(tab, P, tid, TJ * NW);
+  s_tab.load(tab, P, ONE ? 1 : nsp, tid, TJ * NW);
 
   const int n = sd.n, ld = sd.com_ld, np = sd.npad;
   const double L = P.L, invL = P.invL, rc2 = P.rc2;
@@ -400,7 +403,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
       bool in = true;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        u.t.com[side][c][lane] = c3[c];
+        (side ? u.t.comj : u.t.comi)[c][lane] = c3[c];
         in = in && c3[c] >= 0.0 && c3[c] <= L;
       }
       s_sp[side][lane] = sp;
@@ -430,27 +433,28 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   // 1. cut-off bits: wave wv tests columns [16 wv, 16 wv + 16) of row `lane`
   //    (centres in [0, L], the usual case: the image-free form of the same r2)
   {
-    const double xi = u.t.com[0][0][lane], yi = u.t.com[0][1][lane], zi = u.t.com[0][2][lane];
+    const double xi = u.t.comi[0][lane], yi = u.t.comi[1][lane], zi = u.t.comi[2][lane];
     const bool inbox = __builtin_amdgcn_readfirstlane(s_inbox[0] & s_inbox[1]) != 0;
+    // the columns this row may pair with, as bits of the wave's 16: inside
+    // the tile, and on the diagonal item above the row
+    const int j0 = 16 * wv, nv = ncol - j0, s = lane - j0 + 1;
+    unsigned valid = nv >= 16 ? 0xFFFFu : nv > 0 ? (1u << nv) - 1u : 0u;
+    if (diag) valid &= s <= 0 ? 0xFFFFu : s < 16 ? (0xFFFFu << s) & 0xFFFFu : 0u;
+    const double* cj = &u.t.comj[0][j0];
     unsigned part = 0;
     if (inbox) {
       for (int b = 0; b < 16; ++b) {
-        const int jj = 16 * wv + b;
-        const double r2 = min_image_r2(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L);
-        const unsigned ok = (unsigned)(r2 < rlist2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
-        part |= ok << b;
+        const double r2 = min_image_r2(xi, yi, zi, cj[b], cj[TJ + b], cj[2 * TJ + b], L);
+        part |= (unsigned)(r2 < rlist2) << b;
       }
     } else {
       for (int b = 0; b < 16; ++b) {
-        const int jj = 16 * wv + b;
         double dx, dy, dz, r2;
-        min_image(xi, yi, zi, u.t.com[1][0][jj], u.t.com[1][1][jj], u.t.com[1][2][jj], L, invL, dx, dy, dz,
-                  r2);
-        const unsigned ok = (unsigned)(r2 < rlist2) & (unsigned)(jj < ncol) & (unsigned)(!diag || jj > lane);
-        part |= ok << b;
+        min_image(xi, yi, zi, cj[b], cj[TJ + b], cj[2 * TJ + b], L, invL, dx, dy, dz, r2);
+        part |= (unsigned)(r2 < rlist2) << b;
       }
     }
-    s_mpart[wv][lane] = lane < nrow ? part : 0u;
+    s_mpart[wv][lane] = lane < nrow ? part & valid : 0u;
   }
   __syncthreads();
   // row masks rotated so that bit d is column lane + d; wave wv transposes
@@ -487,7 +491,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   Real g_row[6] = {0, 0, 0, 0, 0, 0}, g_col[6] = {0, 0, 0, 0, 0, 0};
   Real(*stage)[TJ] = u.t.stage[wv];
   int* list = s_list[wv];
-  signed char(*keep)[TJ] = u.t.er[wv];
+  unsigned char(*keep)[TJ] = u.t.er[wv];
   for (int q = wv * TJ; q < total; q += NW * TJ) {
     const bool valid = q + lane < total;
     const int qend = min(q + TJ, total);
@@ -498,7 +502,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     for (int dd = dfirst; dd <= dlast; ++dd) {
       const int er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
       if (er >= 0) list[er] = lane | (dd << 6);
-      if (dd - dfirst < kKeepDiags) keep[dd - dfirst][lane] = (signed char)er;
+      if (dd - dfirst < kKeepDiags) keep[dd - dfirst][lane] = (unsigned char)er;
     }
     wave_sync_lds();
     const int pr = list[lane];
@@ -507,8 +511,8 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
 
     const int spi = ONE ? 0 : s_sp[0][row], spj = ONE ? 0 : s_sp[1][col];
     double dx, dy, dz, r2d;
-    min_image(u.t.com[0][0][row], u.t.com[0][1][row], u.t.com[0][2][row], u.t.com[1][0][col],
-              u.t.com[1][1][col], u.t.com[1][2][col], L, invL, dx, dy, dz, r2d);
+    min_image(u.t.comi[0][row], u.t.comi[1][row], u.t.comi[2][row], u.t.comj[0][col], u.t.comj[1][col],
+              u.t.comj[2][col], L, invL, dx, dy, dz, r2d);
     const Real Rx = (Real)dx, Ry = (Real)dy, Rz = (Real)dz;
     const Real R2 = Rx * Rx + Ry * Ry + Rz * Rz;
     Real rec[NR];
@@ -568,19 +572,19 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     // gather: molecule `lane` of tile I at its own entry index; molecule
     // `lane` of tile J is the column of row lane - dd
     for (int dd = dfirst; dd <= dlast; ++dd) {
-      int er, ec;
+      unsigned er, ec;                       // entry index, or 64 and above for none
       if (dd - dfirst < kKeepDiags) {
         er = keep[dd - dfirst][lane];
         ec = keep[dd - dfirst][(lane - dd) & (TJ - 1)];
       } else {
-        er = row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
-        ec = __shfl(er, (lane - dd) & (TJ - 1), TJ);
+        er = (unsigned)row_entry(readlane64(dword, dd), __builtin_amdgcn_readlane(doff, dd) - q);
+        ec = (unsigned)__shfl((int)er, (lane - dd) & (TJ - 1), TJ);
       }
-      if (er >= 0) {
+      if (er < (unsigned)TJ) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) g_row[c] += stage[c][er];
       }
-      if (ec >= 0) {
+      if (ec < (unsigned)TJ) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           g_col[c] -= stage[c][ec];

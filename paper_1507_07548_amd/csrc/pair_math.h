@@ -278,14 +278,18 @@ struct PairTables {
   Real mch[kMaxSp][NCH], mdp[kMaxSp][NDP], mqd[kMaxSp][NQD];   // k_e * magnitude
   int nsite[kMaxSp][kMaxSp];
 
-  __device__ void load(const SpeciesTable* tab, const SysParams& P, int tid, int nthreads) {
-    const int nsp = P.nsp;
-    for (int e = tid; e < nsp * NLJ * nsp * NLJ; e += nthreads) {
-      const int A = e / (NLJ * nsp * NLJ), r = e % (NLJ * nsp * NLJ);
-      const int a = r / (nsp * NLJ), r2 = r % (nsp * NLJ);
-      const int B = r2 / NLJ, b = r2 % NLJ;
-      c6[A * NLJ + a][B * NLJ + b] = (Real)tab->c6[A][a][B][b];
-      c12[A * NLJ + a][B * NLJ + b] = (Real)tab->c12[A][a][B][b];
+  // nsp: the species in use (1 when every molecule is species 0, whatever
+  // the context holds).  The LJ tables are walked over their full size with
+  // compile-time divisors; entries of unused species are left unset.
+  __device__ void load(const SpeciesTable* tab, const SysParams& P, int nsp, int tid, int nthreads) {
+    constexpr int W = kMaxSp * NLJ;
+    for (int e = tid; e < W * W; e += nthreads) {
+      const int r = e / W, c = e % W;
+      const int A = r / NLJ, a = r % NLJ, B = c / NLJ, b = c % NLJ;
+      if (A < nsp && B < nsp) {
+        c6[r][c] = (Real)tab->c6[A][a][B][b];
+        c12[r][c] = (Real)tab->c12[A][a][B][b];
+      }
     }
     for (int e = tid; e < nsp; e += nthreads) {
       const SpeciesDev& D = tab->sp[e];
