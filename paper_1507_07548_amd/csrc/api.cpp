@@ -221,6 +221,7 @@ void build_sys_params(const ms2_ctx* ctx, const ms2_params* p, int nk, SysParams
   s.rc2 = p->rc * p->rc;
   s.V = p->box * p->box * p->box;
   s.ke = p->coulomb_k;
+  s.inv_ke = p->coulomb_k != 0.0 ? 1.0 / p->coulomb_k : 0.0;   // k_e = 0: no electrostatics, not 0 * inf
   s.elec = p->elec;
   s.kmax2 = p->kmax2;
   s.nk = nk;

@@ -108,7 +108,7 @@ __device__ __forceinline__ ElecParams<Real> elec_params(const SysParams& P) {
   E.alpha = (Real)P.alpha;
   E.alpha2 = (Real)P.alpha2;
   E.gpref = (Real)P.gpref;
-  E.inv_ke = (Real)(1.0 / P.ke);
+  E.inv_ke = (Real)P.inv_ke;
   return E;
 }
 
@@ -308,6 +308,21 @@ __device__ __forceinline__ int row_entry(unsigned long long wd, int o_rel) {
   return (on && (unsigned)e < 64u) ? e : -1;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts:
+// Hillis-Steele steps of 1, 2, 4 and 8 lanes inside each row of 16, then the
+// last lane of row 0 (2) is added to row 1 (3) and lane 31 to rows 2 and 3.
+// Lanes whose DPP source lies outside the row, or whose row the row mask
+// leaves out, add 0.
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+  return v;
+}
+
 __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
   const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
@@ -475,12 +490,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   __syncthreads();
   const unsigned long long dword = s_dw[lane];   // lane d: the pairs (l, l + d) of every row l
   const int cnt = __popcll(dword);
-  int incl = cnt;
-#pragma unroll
-  for (int o = 1; o < TJ; o <<= 1) {
-    const int t = __shfl_up(incl, o, TJ);
-    if (lane >= o) incl += t;
-  }
+  const int incl = wave_inclusive_sum(cnt);
   const int doff = incl - cnt;               // lane d: offset of diagonal d
   const int total = __builtin_amdgcn_readlane(incl, TJ - 1);
 

@@ -69,7 +69,7 @@ struct SpeciesTable {
 // Per-system constants derived on the host from ms2_params.
 struct SysParams {
   double L, invL, rc, rc2, V;
-  double ke, krf, crf;
+  double ke, inv_ke, krf, crf;                     // inv_ke = 1 / ke
   double alpha, alpha2, gpref;                     // gpref = 2 alpha / sqrt(pi)
   int elec, kmax2, nk, lrc;
   int precision, cls, nsp;
