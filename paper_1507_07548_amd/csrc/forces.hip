@@ -329,6 +329,15 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, i
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// Workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8),
+// each with its own L2.  This maps the blocks of one XCD to a contiguous run
+// of the n items, so that items sharing a tile (consecutive in the item list)
+// meet in the same L2.  A bijection of [0, n) for any n.
+__device__ __forceinline__ int xcd_local_item(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
 // Orders this wave's LDS accesses before and after (the wave's lanes only).
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -384,7 +393,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   __shared__ int s_list[NW][TJ];          // per wave: row | diagonal << 6 of each entry of the chunk
   __shared__ int s_inbox[2];              // 1: every staged centre of the side lies in [0, L]
 
-  const WorkItem it = items[item_base + blockIdx.x];
+  const WorkItem it = items[item_base + xcd_local_item(blockIdx.x, gridDim.x)];
   const SlotDev& sd = slots[it.slot];
   if (!sd.active) return;
   const SysParams& P = prm[it.slot];
