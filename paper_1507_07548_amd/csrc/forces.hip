@@ -112,6 +112,15 @@ __device__ __forceinline__ ElecParams<Real> elec_params(const SysParams& P) {
   return E;
 }
 
+// Workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8),
+// each with its own L2.  This maps the blocks of one XCD to a contiguous run
+// of the n items, so that items sharing a tile (consecutive in the item list)
+// meet in the same L2.  A bijection of [0, n) for any n.
+__device__ __forceinline__ int xcd_local_item(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
 // fixed-order block sum of the six per-lane scalars; thread 0..5 write them
 template <int NT>
 __device__ __forceinline__ void block_sums(double (*s_red)[NT], const double* v, double* out) {
@@ -156,7 +165,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
   __shared__ PairTables<Real, C> s_tab;
   __shared__ double s_red[W > 1 ? kNumBlockSums : 1][W > 1 ? TJ : 1];
 
-  const WorkItem it = items[item_base + blockIdx.x];
+  const WorkItem it = items[item_base + xcd_local_item(blockIdx.x, gridDim.x)];
   const SlotDev& sd = slots[it.slot];
   if (!sd.active) return;
   const SysParams& P = prm[it.slot];
@@ -327,15 +336,6 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, i
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
   const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
   return ((unsigned long long)hi << 32) | lo;
-}
-
-// Workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8),
-// each with its own L2.  This maps the blocks of one XCD to a contiguous run
-// of the n items, so that items sharing a tile (consecutive in the item list)
-// meet in the same L2.  A bijection of [0, n) for any n.
-__device__ __forceinline__ int xcd_local_item(int b, int n) {
-  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
-  return x * q + min(x, r) + k;
 }
 
 // Orders this wave's LDS accesses before and after (the wave's lanes only).
