@@ -5,12 +5,13 @@
 // lattice, and S(k) is accumulated in FP64.
 //
 //   sk_kernel          (k block of 64) x (64-molecule tile): partial S(k)
-//   sk_reduce_kernel   per system: S(k) over tiles in fixed order, energy and
-//                      atomic virial of the reciprocal sum
+//   sk_reduce_kernel   one thread per k: S(k) over tiles in fixed order and
+//                      the k's energy and atomic-virial terms
 //   kforce_kernel      (64-molecule tile) x (128-k chunk): per-molecule force,
 //                      torque and sum d.F partials
-//   reduce_kspace_kernel per system: adds the partials (fixed order) into the
-//                      caller's force/torque and the sums
+//   reduce_kforce_kernel, reduce_ksums_kernel: add the force partials and the
+//                      per-k terms (fixed order) into the caller's force,
+//                      torque and sums
 // The k set is a half space (k and -k give equal contributions), so every
 // reciprocal term is doubled.
 #include <hip/hip_runtime.h>
@@ -93,44 +94,43 @@ __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slot
   out[1] = im;
 }
 
+// One thread per k: S(k) summed over the molecule tiles in tile order (the
+// loads of four partials issued before their additions), and the k's terms
+// of the reciprocal energy and atomic virial, g(k) |S(k)|^2 and
+// g(k) |S(k)|^2 (1 - k^2 / (2 alpha^2)) with g(k) = exp(-k^2 / (4 alpha^2)) / k^2,
+// for a fixed-order sum over k in reduce_ksums_kernel.  The terms overwrite
+// the tile-0 partial of the same k, which only this thread reads.
 __global__ __launch_bounds__(256) void sk_reduce_kernel(const SlotDev* __restrict__ slots,
                                                         const SysParams* __restrict__ prm) {
-  __shared__ double s_u[256], s_w[256];
-  const SlotDev& sd = slots[blockIdx.x];
-  const SysParams& P = prm[blockIdx.x];
+  const SlotDev& sd = slots[blockIdx.y];
+  const SysParams& P = prm[blockIdx.y];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
-  const int tid = threadIdx.x;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= sd.nk) return;
+  const double2* part = reinterpret_cast<const double2*>(sd.sk_part) + k;
+  const size_t stride = (size_t)sd.nk;
+  double re = 0.0, im = 0.0;
+  int mc = 0;
+  for (; mc + 4 <= sd.mchunks; mc += 4) {
+    const double2 a = part[mc * stride], b = part[(mc + 1) * stride];
+    const double2 c = part[(mc + 2) * stride], d = part[(mc + 3) * stride];
+    re += a.x; im += a.y;
+    re += b.x; im += b.y;
+    re += c.x; im += c.y;
+    re += d.x; im += d.y;
+  }
+  for (; mc < sd.mchunks; ++mc) {
+    const double2 a = part[mc * stride];
+    re += a.x; im += a.y;
+  }
+  sd.sk[2 * k] = re;
+  sd.sk[2 * k + 1] = im;
   const double k2s = (kTwoPi * P.invL) * (kTwoPi * P.invL);
-  double u = 0.0, w = 0.0;
-  for (int k = tid; k < sd.nk; k += 256) {
-    double re = 0.0, im = 0.0;
-    for (int mc = 0; mc < sd.mchunks; ++mc) {
-      re += sd.sk_part[((size_t)mc * sd.nk + k) * 2];
-      im += sd.sk_part[((size_t)mc * sd.nk + k) * 2 + 1];
-    }
-    sd.sk[2 * k] = re;
-    sd.sk[2 * k + 1] = im;
-    const double k2 = k2s * sd.kvec[k].n2;
-    const double g = exp(-k2 / (4.0 * P.alpha2)) / k2;
-    const double s2 = re * re + im * im;
-    u += g * s2;
-    w += g * s2 * (1.0 - k2 / (2.0 * P.alpha2));
-  }
-  s_u[tid] = u;
-  s_w[tid] = w;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-      s_u[tid] += s_u[tid + h];
-      s_w[tid] += s_w[tid + h];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double pre = 2.0 * P.ke * kTwoPi / P.V;  // 2 pi k_e / V, doubled for the half space
-    sd.ksum[0] = pre * s_u[0];
-    sd.ksum[1] = pre * s_w[0];
-  }
+  const double k2 = k2s * sd.kvec[k].n2;
+  const double g = exp(-k2 / (4.0 * P.alpha2)) / k2;
+  const double s2 = re * re + im * im;
+  sd.sk_part[2 * k] = g * s2;
+  sd.sk_part[2 * k + 1] = g * s2 * (1.0 - k2 / (2.0 * P.alpha2));
 }
 
 __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ slots,
@@ -138,6 +138,7 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
                                                     const SpeciesTable* __restrict__ tab) {
   __shared__ double s_re[kKChunk], s_im[kKChunk], s_g[kKChunk];
   __shared__ int s_n[kKChunk][3];
+  __shared__ int s_next[kKChunk];   // 1: k is k - 1 of the chunk plus one step in n_z
   __shared__ double s_red[64];
   const SlotDev& sd = slots[blockIdx.z];
   const SysParams& P = prm[blockIdx.z];
@@ -156,6 +157,12 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
     s_n[e][0] = kv.nx;
     s_n[e][1] = kv.ny;
     s_n[e][2] = kv.nz;
+    int next = 0;
+    if (e > 0) {
+      const KVec kp = sd.kvec[k0 + e - 1];
+      next = kp.nx == kv.nx && kp.ny == kv.ny && kp.nz + 1 == kv.nz;
+    }
+    s_next[e] = next;
   }
   __syncthreads();
   const int i = blockIdx.x * 64 + tid;
@@ -175,9 +182,20 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
                            A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2]};
       const double x = cx + d[0], y = cy + d[1], z = cz + d[2];
       double sx = 0.0, sy = 0.0, sz = 0.0;
+      // along a line of the k set (n_x, n_y fixed, n_z rising by one) the
+      // phase advances by exp(i 2 pi z / L): one complex product; a line's
+      // first k takes the phase directly
+      double ezc, ezs;
+      phase(z * P.invL, ezc, ezs);
+      double c = 1.0, s = 0.0;
       for (int e = 0; e < nkc; ++e) {
-        double c, s;
-        phase((s_n[e][0] * x + s_n[e][1] * y + s_n[e][2] * z) * P.invL, c, s);
+        if (s_next[e]) {
+          const double c1 = c * ezc - s * ezs;
+          s = c * ezs + s * ezc;
+          c = c1;
+        } else {
+          phase((s_n[e][0] * x + s_n[e][1] * y + s_n[e][2] * z) * P.invL, c, s);
+        }
         const double t = s_g[e] * (s * s_re[e] - c * s_im[e]);
         sx += t * s_n[e][0];
         sy += t * s_n[e][1];
@@ -225,24 +243,42 @@ __global__ __launch_bounds__(256) void reduce_kforce_kernel(const SlotDev* __res
 
 __global__ __launch_bounds__(256) void reduce_ksums_kernel(const SlotDev* __restrict__ slots,
                                                            const SysParams* __restrict__ prm) {
-  __shared__ double s_d[256];
+  __shared__ double s_d[256], s_u[256], s_w[256];
   const SlotDev& sd = slots[blockIdx.x];
   const SysParams& P = prm[blockIdx.x];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
   const int tid = threadIdx.x;
+  // sum_a d_a . F_a over the force partials, and the per-k energy and virial
+  // terms over k: each thread a contiguous run, then a tree (fixed order)
   const int nr = sd.kchunks * sd.mtiles;
   const int per = (nr + 255) / 256;
   double d = 0.0;
   for (int t = tid * per; t < min(nr, (tid + 1) * per); ++t) d += sd.kred[t];
+  const int perk = (sd.nk + 255) / 256;
+  double u = 0.0, w = 0.0;
+  for (int k = tid * perk; k < min(sd.nk, (tid + 1) * perk); ++k) {
+    u += sd.sk_part[2 * k];
+    w += sd.sk_part[2 * k + 1];
+  }
   s_d[tid] = d;
+  s_u[tid] = u;
+  s_w[tid] = w;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) s_d[tid] += s_d[tid + h];
+    if (tid < h) {
+      s_d[tid] += s_d[tid + h];
+      s_u[tid] += s_u[tid + h];
+      s_w[tid] += s_w[tid + h];
+    }
     __syncthreads();
   }
   if (tid == 0) {
-    const double w_mol = sd.ksum[1] - s_d[0];  // molecular virial: W_atomic - sum d.F
-    sd.sums[MS2_SUM_U_RECIP] += sd.ksum[0];
+    const double pre = 2.0 * P.ke * kTwoPi / P.V;  // 2 pi k_e / V, doubled for the half space
+    const double u_recip = pre * s_u[0], w_atomic = pre * s_w[0];
+    sd.ksum[0] = u_recip;
+    sd.ksum[1] = w_atomic;
+    const double w_mol = w_atomic - s_d[0];  // molecular virial: W_atomic - sum d.F
+    sd.sums[MS2_SUM_U_RECIP] += u_recip;
     sd.sums[MS2_SUM_VIRIAL] += w_mol;
     sd.sums[MS2_SUM_US] -= w_mol;
   }
@@ -253,7 +289,8 @@ hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const Speci
                          int max_kchunks, hipStream_t st) {
   hipLaunchKernelGGL(sk_kernel, dim3(max_kblocks, max_mchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
-  hipLaunchKernelGGL(sk_reduce_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
+  hipLaunchKernelGGL(sk_reduce_kernel, dim3((64 * max_kblocks + 255) / 256, nslots), dim3(256), 0, st, slots,
+                     prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
   hipLaunchKernelGGL(reduce_kforce_kernel, dim3((64 * max_mtiles + 255) / 256, nslots), dim3(256), 0,
