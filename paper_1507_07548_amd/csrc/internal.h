@@ -16,8 +16,10 @@ struct KVec { int nx, ny, nz, n2; };
 constexpr int kMaxSp = MS2_MAX_SPECIES;
 constexpr int kMaxS = MS2_MAX_SITES;
 constexpr int kNumBlockSums = 9;  // u_lj, u_el, us, uss, npair, nsite, J_q pair part (x, y, z) per work item
-constexpr int kKChunk = 128;      // k vectors per reciprocal-force block
-constexpr int kMolTile = 64;      // molecules per structure-factor block
+// Ewald blocks are single waves running long FP64 chains: short chunks give
+// small systems enough waves in flight.
+constexpr int kKChunk = 32;       // k vectors per reciprocal-force block
+constexpr int kMolTile = 16;      // molecules per structure-factor block (one wave of 64 k)
 constexpr int kMaxRdfTypes = 16;
 
 // Model classes: compile-time upper bounds on the sites of each type per

@@ -4,10 +4,10 @@
 // phases are reduced to [-pi, pi] exactly via the integer period of the k
 // lattice, and S(k) is accumulated in FP64.
 //
-//   sk_kernel          (k block of 64) x (64-molecule tile): partial S(k)
-//   sk_reduce_kernel   one thread per k: S(k) over tiles in fixed order and
+//   sk_kernel          (k block of 64) x (molecule tile): partial S(k)
+//   sk_reduce_kernel   64 k per block: S(k) over tiles in fixed order and
 //                      the k's energy and atomic-virial terms
-//   kforce_kernel      (64-molecule tile) x (128-k chunk): per-molecule force,
+//   kforce_kernel      (64-molecule tile) x (k chunk): per-molecule force,
 //                      torque and sum d.F partials
 //   reduce_kforce_kernel, reduce_ksums_kernel: add the force partials and the
 //                      per-k terms (fixed order) into the caller's force,
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slot
   const int m0 = mc * kMolTile, m1 = min(sd.n, m0 + kMolTile);
   int maxq = 0;
   for (int s = 0; s < P.nsp; ++s) maxq = max(maxq, tab->sp[s].nch);
-  {
+  if (tid < kMolTile) {
     const int i = m0 + tid;
     for (int a = 0; a < maxq; ++a) s_q[tid * kMaxS + a] = 0.0;
     if (i < m1) {
@@ -94,35 +94,48 @@ __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slot
   out[1] = im;
 }
 
-// One thread per k: S(k) summed over the molecule tiles in tile order (the
-// loads of four partials issued before their additions), and the k's terms
-// of the reciprocal energy and atomic virial, g(k) |S(k)|^2 and
-// g(k) |S(k)|^2 (1 - k^2 / (2 alpha^2)) with g(k) = exp(-k^2 / (4 alpha^2)) / k^2,
-// for a fixed-order sum over k in reduce_ksums_kernel.  The terms overwrite
-// the tile-0 partial of the same k, which only this thread reads.
+// S(k) summed over the molecule tiles in a fixed order: a block holds 64 k,
+// and its four waves each sum one consecutive run of the tiles (loads of four
+// partials issued before their additions); the run sums are added in run
+// order.  Then the k's terms of the reciprocal energy and atomic virial,
+// g(k) |S(k)|^2 and g(k) |S(k)|^2 (1 - k^2 / (2 alpha^2)) with
+// g(k) = exp(-k^2 / (4 alpha^2)) / k^2, for a fixed-order sum over k in
+// reduce_ksums_kernel.  The terms overwrite the tile-0 partial of the same
+// k, which only this block reads.
 __global__ __launch_bounds__(256) void sk_reduce_kernel(const SlotDev* __restrict__ slots,
                                                         const SysParams* __restrict__ prm) {
+  __shared__ double s_re[4][64], s_im[4][64];
   const SlotDev& sd = slots[blockIdx.y];
   const SysParams& P = prm[blockIdx.y];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= sd.nk) return;
-  const double2* part = reinterpret_cast<const double2*>(sd.sk_part) + k;
-  const size_t stride = (size_t)sd.nk;
+  const int kl = threadIdx.x & 63, run = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + kl;
+  const bool kin = k < sd.nk;
+  const int len = (sd.mchunks + 3) / 4, t0 = min(sd.mchunks, run * len), t1 = min(sd.mchunks, t0 + len);
   double re = 0.0, im = 0.0;
-  int mc = 0;
-  for (; mc + 4 <= sd.mchunks; mc += 4) {
-    const double2 a = part[mc * stride], b = part[(mc + 1) * stride];
-    const double2 c = part[(mc + 2) * stride], d = part[(mc + 3) * stride];
-    re += a.x; im += a.y;
-    re += b.x; im += b.y;
-    re += c.x; im += c.y;
-    re += d.x; im += d.y;
+  if (kin) {
+    const double2* part = reinterpret_cast<const double2*>(sd.sk_part) + k;
+    const size_t stride = (size_t)sd.nk;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+      const double2 a = part[t * stride], b = part[(t + 1) * stride];
+      const double2 c = part[(t + 2) * stride], d = part[(t + 3) * stride];
+      re += a.x; im += a.y;
+      re += b.x; im += b.y;
+      re += c.x; im += c.y;
+      re += d.x; im += d.y;
+    }
+    for (; t < t1; ++t) {
+      const double2 a = part[t * stride];
+      re += a.x; im += a.y;
+    }
   }
-  for (; mc < sd.mchunks; ++mc) {
-    const double2 a = part[mc * stride];
-    re += a.x; im += a.y;
-  }
+  s_re[run][kl] = re;
+  s_im[run][kl] = im;
+  __syncthreads();
+  if (run != 0 || !kin) return;
+  re = ((s_re[0][kl] + s_re[1][kl]) + s_re[2][kl]) + s_re[3][kl];
+  im = ((s_im[0][kl] + s_im[1][kl]) + s_im[2][kl]) + s_im[3][kl];
   sd.sk[2 * k] = re;
   sd.sk[2 * k + 1] = im;
   const double k2s = (kTwoPi * P.invL) * (kTwoPi * P.invL);
@@ -232,9 +245,24 @@ __global__ __launch_bounds__(256) void reduce_kforce_kernel(const SlotDev* __res
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= sd.n) return;
   const int np = sd.npad, ld = sd.com_ld;
+  // chunk order; the loads of four chunks are issued before their additions
   double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int kc = 0; kc < sd.kchunks; ++kc)
-    for (int c = 0; c < 6; ++c) v[c] += sd.fk[((size_t)kc * 6 + c) * np + i];
+  const double* fk = sd.fk + i;
+  int kc = 0;
+  for (; kc + 4 <= sd.kchunks; kc += 4) {
+    double t[4][6];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t[u][c] = fk[((size_t)(kc + u) * 6 + c) * np];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] += t[u][c];
+  }
+  for (; kc < sd.kchunks; ++kc)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] += fk[((size_t)kc * 6 + c) * np];
   for (int c = 0; c < 3; ++c) {
     sd.force[c * ld + i] += v[c];
     sd.torque[c * ld + i] += v[3 + c];
@@ -289,8 +317,7 @@ hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const Speci
                          int max_kchunks, hipStream_t st) {
   hipLaunchKernelGGL(sk_kernel, dim3(max_kblocks, max_mchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
-  hipLaunchKernelGGL(sk_reduce_kernel, dim3((64 * max_kblocks + 255) / 256, nslots), dim3(256), 0, st, slots,
-                     prm);
+  hipLaunchKernelGGL(sk_reduce_kernel, dim3(max_kblocks, nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
   hipLaunchKernelGGL(reduce_kforce_kernel, dim3((64 * max_mtiles + 255) / 256, nslots), dim3(256), 0,
