@@ -308,8 +308,7 @@ ms2_status ms2_slot_status(ms2_batch* batch, int32_t slot, int64_t* steps_done,
  * the context's model class, the precision, the launch mode (0: one system
  * per launch, 1: batched) and the size bucket floor(log2 n) -- never on which
  * other systems share a launch.  Until ms2_autotune or ms2_set_tile_config
- * sets a bucket, one system per launch uses row-owned items of one wave and
- * batched launches use symmetric items. */
+ * sets a bucket, both modes use symmetric items. */
 ms2_status ms2_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,
                            int32_t* wave_rows, int32_t* j_chunk);
 ms2_status ms2_set_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,

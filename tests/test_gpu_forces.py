@@ -47,11 +47,35 @@ def say(*a):
     sys.stdout.flush()
 
 
-def compare(system, precision, ctx=None, label=""):
-    say(f"[gpu] {label} n={system.n} precision={'fp32' if precision else 'fp64'}")
-    ctx = ctx or ms2.Context(system.species)
+# the single-system shapes the main parity cases run in: the library's
+# default (symmetric tile pairs) and row-owned items of one wave
+SHAPES = ["default", "row-owned"]
+_oracle_memo = {}
+
+
+def oracle_result(system):
+    """oracle.evaluate, computed once per distinct input (the shape
+    parametrisation evaluates the same system twice)."""
+    key = (system.com.tobytes(), system.quat.tobytes(), np.asarray(system.species_idx).tobytes(),
+           repr(system.params), repr(system.species))
+    if key not in _oracle_memo:
+        _oracle_memo[key] = oracle.evaluate(system)
+    return _oracle_memo[key]
+
+
+def shaped_ctx(system, precision, shape):
+    ctx = ms2.Context(system.species)
+    if shape == "row-owned":
+        n = system.n
+        ctx.set_tile_config(n, precision, 1, 64 * max(1, (n + 1023) // 1024), mode=0)
+    return ctx
+
+
+def compare(system, precision, ctx=None, label="", shape="default"):
+    say(f"[gpu] {label} n={system.n} precision={'fp32' if precision else 'fp64'} shape={shape}")
+    ctx = ctx or shaped_ctx(system, precision, shape)
     f, t, s = ms2.evaluate(ctx, system, precision)
-    fo, to, so = oracle.evaluate(system)
+    fo, to, so = oracle_result(system)
     rms_f = np.sqrt((fo ** 2).sum(1).mean())
     rms_t = np.sqrt((to ** 2).sum(1).mean())
     rms_f = rms_f if rms_f > 0 else 1.0     # no pair inside the cut-off: absolute error
@@ -80,17 +104,19 @@ def check_sums(s, so, rtol, atol_frac, slots=range(10)):
 # --------------------------------------------------------------------------
 # the three single-system workloads
 # --------------------------------------------------------------------------
-def test_lj_fluid_fp64_parity():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_lj_fluid_fp64_parity(shape):
     # the perfect FCC start has zero net force on every molecule; displace it
     s = I.jittered(I.lj_fluid(), 0.05, seed=11)
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="lj_fluid")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="lj_fluid", shape=shape)
     assert ef < 1e-11
     check_sums(su, so, 1e-11, 1e-12)
 
 
-def test_lj_fluid_lattice_start():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_lj_fluid_lattice_start(shape):
     s = I.lj_fluid()
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="lj_fluid lattice")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="lj_fluid lattice", shape=shape)
     assert np.abs(f).max() < 1e-11 and np.abs(fo).max() < 1e-11
     check_sums(su, so, 1e-11, 1e-12)
     f32, _, s32 = ms2.evaluate(ms2.Context(s.species), s, ms2.FP32)
@@ -98,45 +124,49 @@ def test_lj_fluid_lattice_start():
     assert energy_error(s32, so) < 1e-6      # coherent rounding on a lattice
 
 
-def test_quadrupolar_fluid_fp64_parity():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_quadrupolar_fluid_fp64_parity(shape):
     s = I.quadrupolar_fluid()
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="quadrupolar_fluid")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="quadrupolar_fluid", shape=shape)
     assert ef < 1e-11 and et < 1e-11, (ef, et)
     check_sums(su, so, 1e-11, 1e-12)
 
 
-def test_quadrupolar_fluid_fp32_parity():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_quadrupolar_fluid_fp32_parity(shape):
     s = I.quadrupolar_fluid()
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="quadrupolar_fluid")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="quadrupolar_fluid", shape=shape)
     say(f"  fp32 max|dF|/rms {ef:.3e} max|dT|/rms {et:.3e}")
     assert ef < 1e-5 and et < 1e-5
     assert energy_error(su, so) < 1e-6           # FCC start
     check_sums(su, so, 1e-6, 1e-8, slots=[5, 6, 7, 8, 9])
     sj = I.jittered(s, 0.1, seed=5)               # disordered
-    f, t, su, fo, to, so, ef, et = compare(sj, ms2.FP32, label="quadrupolar_fluid jittered")
+    f, t, su, fo, to, so, ef, et = compare(sj, ms2.FP32, label="quadrupolar_fluid jittered", shape=shape)
     assert ef < 1e-5 and et < 1e-5
     assert energy_error(su, so) < 5e-8
     check_sums(su, so, 1e-6, 1e-8, slots=[5, 6, 7, 8, 9])
 
 
-def test_ionic_solution_fp64_parity():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ionic_solution_fp64_parity(shape):
     s = I.ionic_solution()
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="ionic_solution")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, label="ionic_solution", shape=shape)
     say(f"  fp64 max|dF|/rms {ef:.3e} max|dT|/rms {et:.3e}")
     assert ef < 1e-11 and et < 1e-11
     check_sums(su, so, 1e-11, 1e-12)
 
 
-def test_ionic_solution_fp32_parity():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ionic_solution_fp32_parity(shape):
     s = I.ionic_solution()
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="ionic_solution")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="ionic_solution", shape=shape)
     say(f"  fp32 max|dF|/rms {ef:.3e} max|dT|/rms {et:.3e}")
     assert ef < 1e-5 and et < 1e-5
     assert energy_error(su, so) < 1e-6
     # reciprocal part is FP64 in both precision forms
     assert abs(su[2] - so[2]) <= 1e-10 * abs(so[2])
     sj = I.jittered(s, 0.3, seed=6)
-    f, t, su, fo, to, so, ef, et = compare(sj, ms2.FP32, label="ionic_solution jittered")
+    f, t, su, fo, to, so, ef, et = compare(sj, ms2.FP32, label="ionic_solution jittered", shape=shape)
     assert ef < 1e-5 and et < 1e-5
     assert energy_error(su, so) < 2e-7
 
@@ -146,29 +176,32 @@ def test_ionic_solution_fp32_parity():
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n", [2, 3, 63, 65, 130, 257])
 @pytest.mark.parametrize("elec", [I.ELEC_NONE, I.ELEC_RF])
-def test_offset_multipoles_ragged(n, elec):
+@pytest.mark.parametrize("shape", SHAPES)
+def test_offset_multipoles_ragged(n, elec, shape):
     box = 1.4 * n ** (1 / 3) + 2.5
     s = small_system([offset_multipoles(), I.stockmayer()], n, box, 0.45 * box, seed=n + 7 * elec,
                      elec=elec, eps_rf=25.0)
     for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
-        f, t, su, fo, to, so, ef, et = compare(s, prec, label=f"offset elec={elec}")
+        f, t, su, fo, to, so, ef, et = compare(s, prec, label=f"offset elec={elec}", shape=shape)
         assert ef < tol and et < tol, (ef, et)
 
 
 @pytest.mark.parametrize("n", [2, 37, 200])
-def test_ewald_mixture_ragged(n):
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ewald_mixture_ragged(n, shape):
     box = 1.3 * n ** (1 / 3) + 3.0
     s = small_system(ionic_pair_species(), n, box, 0.45 * box, seed=n, elec=I.ELEC_EWALD,
                      alpha=6.0 / box, kmax2=30)
     for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
-        f, t, su, fo, to, so, ef, et = compare(s, prec, label="ewald mixture")
+        f, t, su, fo, to, so, ef, et = compare(s, prec, label="ewald mixture", shape=shape)
         assert ef < tol and et < tol, (ef, et)
         assert abs(su[2] - so[2]) <= 1e-10 * abs(so[2])
 
 
-def test_no_pair_inside_cutoff():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_no_pair_inside_cutoff(shape):
     s = small_system([I.two_center_lj_quadrupole()], 8, 40.0, 3.0, seed=1, elec=I.ELEC_RF, jitter=0.0)
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="dilute")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="dilute", shape=shape)
     assert su[NPAIR] == 0 and np.abs(f).max() == 0.0 and su[0] == 0.0
 
 
@@ -176,9 +209,10 @@ def test_no_pair_inside_cutoff():
 # full sizes: N = 4000 and 8192 (largest state point and serving size)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n", [4000, 8192])
-def test_large_quadrupolar_fluid_fp32(n):
+@pytest.mark.parametrize("shape", SHAPES)
+def test_large_quadrupolar_fluid_fp32(n, shape):
     s = I.jittered(I.quadrupolar_fluid(n=n, density=0.45), 0.1, seed=n)
-    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="large")
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, label="large", shape=shape)
     say(f"  fp32 n={n} max|dF|/rms {ef:.3e}")
     assert ef < 1e-5 and et < 1e-5
     assert energy_error(su, so) < 1e-8
