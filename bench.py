@@ -13,9 +13,11 @@ corrector, isokinetic thermostat, Lustig moment sums):
 
 Printed JSON line: site-pair interactions/s of the batched form (value), MD
 steps/s, the plain one-system-per-launch form on a sample of the same
-systems, the same batched workload in FP64, a serving trace (p50/p99
-latency), the pair kernel's roofline (HIP events around its launches inside
-the timed graph) and the oracle timed on the host as a CPU baseline.
+systems, the same batched workload in FP64, the ionic-solution system with
+Ewald (real-space and reciprocal calls timed apart, and its MD step rate), a
+serving trace (p50/p99 latency), the pair kernel's roofline (HIP events
+around its launches inside the timed graph) and the oracle timed on the host
+as a CPU baseline.
 """
 import argparse
 import json
@@ -169,6 +171,53 @@ def precision_form(ms2, torch, ctx, systems, K, W, graph):
             "form": "FP64 site arithmetic and sums, same systems, symmetric tile pairs, graph"}
 
 
+def ionic_form(ms2, torch, inputs, K, W):
+    """The ionic-solution configuration (900 water-like molecules + 50 cation/anion
+    pairs, Ewald alpha = 5.6 / L with 0 < n^2 <= 64, rc = 0.48 L, tin-foil; FP32 pairs,
+    FP64 k-space): one force evaluation timed by its two calls with HIP events, then
+    Gear NVT steps of the one system with the 400-bin RDF every 10 steps, graph replay."""
+    log("[bench] ionic solution with Ewald")
+    s = inputs.ionic_solution()
+    s.md.n_steps = max(s.md.n_steps, W + K + 2)
+    ctx = ms2.Context(s.species)
+    d = ms2.DeviceSystem(s)
+    p = ms2.params_struct(s.params, ms2.FP32)
+    for _ in range(3):
+        ctx.forces(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+        ctx.ewald_kspace(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 20
+    ev[0].record()
+    for _ in range(reps):
+        ctx.forces(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    ev[1].record()
+    for _ in range(reps):
+        ctx.ewald_kspace(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    ev[2].record()
+    torch.cuda.synchronize()
+    b = ms2.Batch(ctx, 1)
+    slot = b.admit(s, ms2.FP32)
+    b.step(W if W > 0 else 1, graph=True)
+    torch.cuda.synchronize()
+    pb = b.sample(slot, state=False)
+    t0 = time.perf_counter()
+    b.step(K, graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pa = b.sample(slot, state=False)
+    assert pa["status"] == 0 and pa["steps_done"] == pb["steps_done"] + K
+    sp = pa["site_pairs_total"] - pb["site_pairs_total"]
+    b.close()
+    ctx.close()
+    return {"workload": "ionic_solution_ewald", "molecules": s.n, "k_vectors_half_space": 1054,
+            "forces_us": ev[0].elapsed_time(ev[1]) / reps * 1e3,
+            "kspace_us": ev[1].elapsed_time(ev[2]) / reps * 1e3,
+            "md_ms_per_step": (t1 - t0) / K * 1e3, "site_pairs_per_s": sp / (t1 - t0),
+            "form": "one system; forces = ms2_forces (real space, FP32 pairs), kspace = "
+                    "ms2_ewald_kspace (FP64); MD step = Gear NVT + RDF every 10 steps, graph"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +229,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form of the batched workload")
+    ap.add_argument("--no-ewald", action="store_true", help="skip the ionic-solution (Ewald) timing")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=400)
     ap.add_argument("--no-graph", action="store_true",
@@ -264,6 +314,7 @@ def main():
     sample = systems[: args.plain_sample]
     plain = plain_form(ms2, torch, ctx, sample, K, W) if sample else None
     fp64 = None if args.no_fp64 else precision_form(ms2, torch, ctx, systems, K, W, graph)
+    ewald = None if args.no_ewald else ionic_form(ms2, torch, inputs, K, W)
     serving = None if args.no_serve else serve_trace(args.serve_requests, args.serve_steps)
 
     line = {
@@ -299,6 +350,8 @@ def main():
         line["batched_over_plain"] = value / plain["value"]
     if fp64 is not None:
         line["fp64"] = fp64
+    if ewald is not None:
+        line["ewald"] = ewald
     if serving is not None:
         line["serving"] = serving
     if not args.no_cpu_baseline:

@@ -237,36 +237,36 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
   if (tid == 0) sd.kred[(size_t)kc * sd.mtiles + blockIdx.x] = s_red[0];
 }
 
+// One thread per (component, molecule): the grid's x holds six runs of
+// molecule blocks, one per force/torque component; the chunk partials are
+// added in chunk order (the loads of four chunks issued before their
+// additions).
 __global__ __launch_bounds__(256) void reduce_kforce_kernel(const SlotDev* __restrict__ slots,
                                                             const SysParams* __restrict__ prm) {
   const SlotDev& sd = slots[blockIdx.y];
   const SysParams& P = prm[blockIdx.y];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int mb = gridDim.x / 6, c = blockIdx.x / mb;
+  const int i = (blockIdx.x - c * mb) * 256 + threadIdx.x;
   if (i >= sd.n) return;
   const int np = sd.npad, ld = sd.com_ld;
-  // chunk order; the loads of four chunks are issued before their additions
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  const double* fk = sd.fk + i;
+  const double* fk = sd.fk + (size_t)c * np + i;
+  const size_t stride = (size_t)6 * np;
+  double v = 0.0;
   int kc = 0;
   for (; kc + 4 <= sd.kchunks; kc += 4) {
-    double t[4][6];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) t[u][c] = fk[((size_t)(kc + u) * 6 + c) * np];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] += t[u][c];
+    const double a = fk[kc * stride], b = fk[(kc + 1) * stride];
+    const double e = fk[(kc + 2) * stride], f = fk[(kc + 3) * stride];
+    v += a;
+    v += b;
+    v += e;
+    v += f;
   }
-  for (; kc < sd.kchunks; ++kc)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] += fk[((size_t)kc * 6 + c) * np];
-  for (int c = 0; c < 3; ++c) {
-    sd.force[c * ld + i] += v[c];
-    sd.torque[c * ld + i] += v[3 + c];
-  }
+  for (; kc < sd.kchunks; ++kc) v += fk[kc * stride];
+  if (c < 3)
+    sd.force[c * ld + i] += v;
+  else
+    sd.torque[(c - 3) * ld + i] += v;
 }
 
 __global__ __launch_bounds__(256) void reduce_ksums_kernel(const SlotDev* __restrict__ slots,
@@ -320,7 +320,7 @@ hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const Speci
   hipLaunchKernelGGL(sk_reduce_kernel, dim3(max_kblocks, nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
-  hipLaunchKernelGGL(reduce_kforce_kernel, dim3((64 * max_mtiles + 255) / 256, nslots), dim3(256), 0,
+  hipLaunchKernelGGL(reduce_kforce_kernel, dim3(6 * ((64 * max_mtiles + 255) / 256), nslots), dim3(256), 0,
                      st, slots, prm);
   hipLaunchKernelGGL(reduce_ksums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();

@@ -7,6 +7,9 @@
   counters <counters.csv> <kernel substring>
       every counter of a --pmc run per launch, averaged over the
       largest-grid dispatches whose name holds the substring.
+  select <results.db> <substring;substring;...>
+      per kernel and grid size, calls and durations of the kernels whose
+      name holds one of the ';'-separated substrings.
   traffic <fetch.csv> <write.csv> <copy_bytes> <kernel substring>
       HBM bytes per launch of the largest-grid dispatches whose name holds
       the substring, from two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
@@ -56,6 +59,19 @@ def largest_grid(db_path, substring):
     gmax = max(g for g, _ in rows)
     d = [t for g, t in rows if g == gmax]
     return len(d), sum(d) / len(d) / 1e3, gmax
+
+
+def select(db_path, substrings):
+    """Per kernel and grid size, for the kernels whose name holds one of the
+    substrings: calls, average and total duration."""
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, grid_x * grid_y * grid_z, count(*), avg(duration), sum(duration) "
+                       "from kernels group by name, grid_x * grid_y * grid_z").fetchall()
+    out = ["| kernel | grid (work-items) | calls | avg us | total ms |", "|---|---|---|---|---|"]
+    for name, grid, calls, avg, tot in sorted(rows, key=lambda r: -r[4]):
+        if any(sub in name for sub in substrings):
+            out.append(f"| `{name.split('(')[0]}` | {grid} | {calls} | {avg / 1e3:.1f} | {tot / 1e6:.2f} |")
+    return "\n".join(out)
 
 
 def _dispatches(csv_path, counter):
@@ -132,6 +148,8 @@ if __name__ == "__main__":
         print(counters(sys.argv[2], sys.argv[3]))
     elif len(sys.argv) >= 2 and sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5]))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "select":
+        print(select(sys.argv[2], sys.argv[3].split(";")))
     elif len(sys.argv) >= 2 and sys.argv[1] == "kernels":
         print(summarize(sys.argv[2]))
         if len(sys.argv) >= 4:
