@@ -39,7 +39,7 @@ hipError_t launch_md_begin(const SlotDev* slots, MDDev* md, const SysParams* prm
 hipError_t launch_residence(const SlotDev* slots, MDDev* md, const SysParams* prm, int slot_base,
                             int nslots, int max_solute, hipStream_t st);
 hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const SpeciesTable* tab,
-                         int nslots, hipStream_t st);
+                         int nslots, int max_n, hipStream_t st);
 hipError_t launch_rdf(int waves, const WorkItem* items, int base, int count, const SlotDev* slots,
                       const MDDev* md, const SysParams* prm, const SpeciesTable* tab,
                       hipStream_t st);
@@ -58,7 +58,7 @@ namespace {
 // byte layout of one slot's allocation
 struct SlotLayout {
   size_t species, sites, pf, bsum, force, torque, sums, r, q, w, vel;
-  size_t skp, sk, fk, kred, ksum, moments, rdf, acf_v, acf_j, acf_cnt, origin_v, origin_j,
+  size_t skp, sk, fk, kred, ksum, moments, md_part, rdf, acf_v, acf_j, acf_cnt, origin_v, origin_j,
       origin_t0;
   size_t res_idx, res_state, res_n0, res_part, res_inside, res_acf, res_cnt;
   size_t hf_kin, hf_jq, acf_q, acf_q_cnt, origin_jq, origin_jq_valid;
@@ -101,6 +101,7 @@ SlotLayout layout_of(const SlotShape& s) {
   L.kred = take((size_t)s.kchunks * s.mtiles * 8);
   L.ksum = take(4 * 8);
   L.moments = take(kNumMoments * 8);
+  L.md_part = take((n + kMdBlock - 1) / kMdBlock * 8 * 8);
   L.rdf = take((size_t)s.rdf_ntp * s.rdf_bins * 8);
   L.acf_v = take((size_t)s.acf_nlag * 8);
   L.acf_j = take((size_t)s.acf_nlag * 8);
@@ -365,7 +366,7 @@ ms2_status enqueue_step(ms2_batch* b, hipStream_t st, int timed_step) {
   MS2_HIP(launch_md_begin(ds, dm, dp, ctx->d_tab, b->max_slots, b->max_n, st));
   ms2_status s = enqueue_forces(b, st, timed_step);
   if (s != MS2_OK) return s;
-  MS2_HIP(launch_md_end(ds, dm, dp, ctx->d_tab, b->max_slots, st));
+  MS2_HIP(launch_md_end(ds, dm, dp, ctx->d_tab, b->max_slots, b->max_n, st));
   if (b->any_rdf)
     for (auto& g : b->groups)
       MS2_HIP(launch_rdf(g.waves, (const WorkItem*)b->d_items.p, g.begin, g.end - g.begin, ds, dm, dp,
@@ -571,6 +572,7 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   m.w = (double*)(base + lay.w);
   m.vel = (double*)(base + lay.vel);
   m.moments = (double*)(base + lay.moments);
+  m.md_part = (double*)(base + lay.md_part);
   m.rdf = (unsigned long long*)(base + lay.rdf);
   m.acf_v = (double*)(base + lay.acf_v);
   m.acf_j = (double*)(base + lay.acf_j);

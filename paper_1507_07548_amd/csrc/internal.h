@@ -131,7 +131,8 @@ struct WorkItem {
 };
 
 constexpr int kNumMoments = 11;   // N, X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ
-constexpr int kMdThreads = 1024;  // one block per slot for the O(N) step kernels
+constexpr int kMdThreads = 1024;  // one block per slot for the per-system passes of the MD step
+constexpr int kMdBlock = 256;     // threads per block of the per-molecule MD kernels
 
 // Per-slot integrator and sampler state (device memory).
 struct MDDev {
@@ -147,12 +148,14 @@ struct MDDev {
   int n_origins, rdf_ntp, pad0, pad1;
   double rdf_rmax, rdf_inv_dr, rdf_reach2, u0;
   double ekin_tr, ekin_rot;
+  double scale_tr, scale_rot;  // this step's isokinetic factors (1 without a thermostat)
   double pairs_total, site_pairs_total;
   double* r;             // Gear translation [5][3][n] (r, dt v, dt^2 a/2, ...); VV: r[0]
   double* q;             // Gear quaternion  [5][4][n]
   double* w;             // Gear body angular velocity [5][3][n]
   double* vel;           // velocities [3][n] (VV state; Gear: r1/dt for the samplers)
   double* moments;       // [kNumMoments]
+  double* md_part;       // [ceil(n / kMdBlock)][8] per-block partial sums of the step's end
   unsigned long long* rdf;  // [rdf_ntp][rdf_bins] counts
   double* acf_v;         // [acf_nlag]
   double* acf_j;         // [acf_nlag]

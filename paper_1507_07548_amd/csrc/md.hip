@@ -6,19 +6,22 @@
 //                      evaluation; kinetic energies; ACF sample at t = 0
 //   md_begin_kernel    Gear predictor (Pascal triangle) and unit-quaternion
 //                      projection, or the first velocity-Verlet kick + drift
-//   md_end_kernel      Gear corrector (5-value coefficients for second-order
-//                      translation and first-order quaternion/Euler systems),
-//                      or the second kick; isokinetic rescaling; Lustig moment
-//                      sums (the paper's Sec. 3, Eq. 1 needs averages of U,
-//                      dU/dV, d2U/dV2 and their products); velocity and
-//                      electric-current autocorrelation on the extended time
-//                      step (Sec. 4; Sec. 5, Eqs. 3-4)
+//   md_correct_kernel, md_thermo_kernel, md_rescale_kernel, md_sample_kernel
+//                      the step's end: Gear corrector (5-value coefficients
+//                      for second-order translation and first-order
+//                      quaternion/Euler systems) or the second kick;
+//                      isokinetic rescaling; Lustig moment sums (the paper's
+//                      Sec. 3, Eq. 1 needs averages of U, dU/dV, d2U/dV2 and
+//                      their products); velocity and electric-current
+//                      autocorrelation on the extended time step (Sec. 4;
+//                      Sec. 5, Eqs. 3-4)
 //   rdf_kernel         site-site radial distribution histogram between LJ
 //                      sites (Sec. 5, Eq. 2), FP64 distances, integer counts
 //   residence_kernel   residence-time correlation and solvation number
 //                      (Sec. 5, Eqs. 7-8) on the extended time step
-// The O(N) kernels use one 1024-thread block per slot so that every
-// reduction (kinetic energy, ACF dot products) is a fixed in-block tree.
+// Every reduction (kinetic energy, ACF dot products) is a fixed-order tree:
+// in-block for the per-system passes (one 1024-thread block per slot), block
+// partials summed in block order for the per-molecule kernels.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -274,151 +277,224 @@ __global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMdThreads) void md_end_kernel(SlotDev* slots, MDDev* md,
-                                                            const SysParams* __restrict__ prm,
-                                                            const SpeciesTable* __restrict__ tab) {
-  __shared__ double red[kMdThreads];
-  SlotDev& sd = slots[blockIdx.x];
-  MDDev& m = md[blockIdx.x];
-  if (!m.active) {
-    // a finished slot samples nothing more (its last RDF sample was taken
-    // right after the step that ended it)
-    if (threadIdx.x == 0) m.rdf_due = 0;
-    return;
+// End of the step, in four launches so that the per-molecule work spreads
+// over many blocks of one system:
+//   md_correct_kernel  (molecule blocks x slots) heat-flux kinetic part of the
+//                      predicted state when due, corrector (or second kick),
+//                      per-block fixed-order partials of sum m v^2, sum I w^2
+//                      and the heat-flux part
+//   md_thermo_kernel   (slot) partials summed in block order; isokinetic
+//                      factors; kinetic energies, totals, Lustig moments,
+//                      RDF flag, status
+//   md_rescale_kernel  (molecule blocks x slots) applies the factors
+//   md_sample_kernel   (slot) ACF sample when due; step count, end of run
+// ---------------------------------------------------------------------------
+
+// fixed-order sums of NV values over the kMdBlock threads of a block; every
+// thread gets the sums
+template <int NV>
+__device__ void block_sums(double* v, double (*red)[kMdBlock]) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < NV; ++k) red[k][tid] = v[k];
+  __syncthreads();
+  for (int h = kMdBlock / 2; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int k = 0; k < NV; ++k) red[k][tid] += red[k][tid + h];
+    __syncthreads();
   }
-  const SysParams& P = prm[blockIdx.x];
-  const int tid = threadIdx.x, n = sd.n, np = sd.com_ld, ld = sd.com_ld;
+  for (int k = 0; k < NV; ++k) v[k] = red[k][0];
+}
+
+__device__ __forceinline__ bool hf_due(const MDDev& m) {
+  return m.hf_on && m.acf_every > 0 && (m.steps_done + 1) % m.acf_every == 0;
+}
+
+// Gear corrector of molecule i (5-value coefficients ct for the second-order
+// translation, cr for the first-order quaternion and Euler systems; the
+// state arrays are distinct allocations, passed as restrict pointers so that
+// loads may pass stores), or the second velocity-Verlet kick
+__device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDev& D, const SysParams& P, int i,
+                                                 int np, int ld, double* __restrict__ gr, double* __restrict__ gw,
+                                                 double* __restrict__ gq, double* __restrict__ gv,
+                                                 const double* __restrict__ gf, const double* __restrict__ gt) {
   const double dt = m.dt;
   const double ct[5] = {19.0 / 120.0, 3.0 / 4.0, 1.0, 1.0 / 2.0, 1.0 / 12.0};
   const double cr[5] = {251.0 / 720.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0};
-  double* v = m.vel;
-  if (m.hf_on && m.acf_every > 0 && (m.steps_done + 1) % m.acf_every == 0) {
-    // heat flux of this step's force evaluation (still the predicted state):
-    // sum_k (m v^2/2 + w.I.w/2 - h_k) v_k plus the pair part from the pair kernel
-    double jk[3] = {0.0, 0.0, 0.0};
-    for (int i = tid; i < n; i += kMdThreads) {
-      const int spi = clamp_species(sd.species[i], tab->nsp);
-      const SpeciesDev& D = tab->sp[spi];
+  if (m.integrator == MS2_GEAR) {
+    for (int c = 0; c < 3; ++c) {
+      const double delta = 0.5 * dt * dt * gf[c * ld + i] / D.mass - gr[(2 * 3 + c) * np + i];
+      for (int d = 0; d < 5; ++d) gr[(d * 3 + c) * np + i] += ct[d] * delta;
+    }
+    if (m.rotating) {
+      double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
+      for (int c = 0; c < 4; ++c) q[c] = gq[c * np + i];
+      for (int c = 0; c < 3; ++c) {
+        w[c] = gw[c * np + i];
+        tq[c] = gt[c * ld + i];
+      }
+      qrot(q[0], q[1], q[2], q[3], A);
+      body_torque(A, tq, tb);
+      euler_rate(D.inertia, tb, w, wd);
+      quat_rate(q, w, qd);
+      for (int c = 0; c < 3; ++c) {
+        const double delta = dt * wd[c] - gw[(1 * 3 + c) * np + i];
+        for (int d = 0; d < 5; ++d) gw[(d * 3 + c) * np + i] += cr[d] * delta;
+      }
+      double q0[4];
+      for (int c = 0; c < 4; ++c) {
+        const double delta = dt * qd[c] - gq[(1 * 4 + c) * np + i];
+        for (int d = 0; d < 5; ++d) gq[(d * 4 + c) * np + i] += cr[d] * delta;
+        q0[c] = gq[c * np + i];
+      }
+      const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+      for (int c = 0; c < 4; ++c) gq[c * np + i] = q0[c] / nq;
+    }
+    for (int c = 0; c < 3; ++c) {
+      gr[c * np + i] = wrap(gr[c * np + i], P.L, P.invL);
+      gv[c * np + i] = gr[(1 * 3 + c) * np + i] / dt;
+    }
+  } else {
+    const double h = 0.5 * dt / D.mass;
+    for (int c = 0; c < 3; ++c) gv[c * np + i] += h * gf[c * ld + i];
+  }
+}
+
+__global__ __launch_bounds__(kMdBlock) void md_correct_kernel(SlotDev* slots, MDDev* md,
+                                                              const SysParams* __restrict__ prm,
+                                                              const SpeciesTable* __restrict__ tab) {
+  __shared__ double red[5][kMdBlock];
+  SlotDev& sd = slots[blockIdx.y];
+  MDDev& m = md[blockIdx.y];
+  const int n = sd.n;
+  if (!m.active || (int)blockIdx.x * kMdBlock >= n) return;   // uniform over the block
+  const SysParams& P = prm[blockIdx.y];
+  const int i = blockIdx.x * kMdBlock + threadIdx.x, np = sd.com_ld, ld = sd.com_ld;
+  double part[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum m v^2, sum I w^2, heat-flux kinetic part
+  if (i < n) {
+    const int spi = clamp_species(sd.species[i], tab->nsp);
+    const SpeciesDev& D = tab->sp[spi];
+    double* v = m.vel;
+    if (hf_due(m)) {
+      // heat flux of this step's force evaluation (still the predicted
+      // state): (m v^2/2 + w.I.w/2 - h_k) v_k of the molecule
       double vi[3], e = 0.0;
       for (int c = 0; c < 3; ++c) {
-        vi[c] = m.integrator == MS2_GEAR ? m.r[(1 * 3 + c) * np + i] / dt : v[c * np + i];
+        vi[c] = m.integrator == MS2_GEAR ? m.r[(1 * 3 + c) * np + i] / m.dt : v[c * np + i];
         e += 0.5 * D.mass * vi[c] * vi[c];
       }
       if (m.integrator == MS2_GEAR && m.rotating)
         for (int c = 0; c < 3; ++c) e += 0.5 * D.inertia[c] * m.w[c * np + i] * m.w[c * np + i];
       e -= m.h_partial[spi];
-      for (int c = 0; c < 3; ++c) jk[c] += e * vi[c];
+      for (int c = 0; c < 3; ++c) part[2 + c] = e * vi[c];
     }
+    correct_molecule(m, D, P, i, np, ld, m.r, m.w, m.q, v, sd.force, sd.torque);
     for (int c = 0; c < 3; ++c) {
-      const double t = block_sum(jk[c], red);
-      if (tid == 0) m.jq_now[c] = t + sd.jq[c];
+      part[0] += D.mass * v[c * np + i] * v[c * np + i];
+      if (m.rotating) part[1] += D.inertia[c] * m.w[c * np + i] * m.w[c * np + i];
     }
-    __syncthreads();
   }
-  // corrector (the state arrays are distinct allocations: each loop is a
-  // function of restrict pointers, so loads may pass stores)
-  auto correct = [&](double* __restrict__ gr, double* __restrict__ gw, double* __restrict__ gq,
-                     double* __restrict__ gv, const double* __restrict__ gf, const double* __restrict__ gt) {
-    for (int i = tid; i < n; i += kMdThreads) {
-      const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
-      if (m.integrator == MS2_GEAR) {
-        for (int c = 0; c < 3; ++c) {
-          const double delta = 0.5 * dt * dt * gf[c * ld + i] / D.mass - gr[(2 * 3 + c) * np + i];
-          for (int d = 0; d < 5; ++d) gr[(d * 3 + c) * np + i] += ct[d] * delta;
-        }
-        if (m.rotating) {
-          double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
-          for (int c = 0; c < 4; ++c) q[c] = gq[c * np + i];
-          for (int c = 0; c < 3; ++c) {
-            w[c] = gw[c * np + i];
-            tq[c] = gt[c * ld + i];
-          }
-          qrot(q[0], q[1], q[2], q[3], A);
-          body_torque(A, tq, tb);
-          euler_rate(D.inertia, tb, w, wd);
-          quat_rate(q, w, qd);
-          for (int c = 0; c < 3; ++c) {
-            const double delta = dt * wd[c] - gw[(1 * 3 + c) * np + i];
-            for (int d = 0; d < 5; ++d) gw[(d * 3 + c) * np + i] += cr[d] * delta;
-          }
-          double q0[4];
-          for (int c = 0; c < 4; ++c) {
-            const double delta = dt * qd[c] - gq[(1 * 4 + c) * np + i];
-            for (int d = 0; d < 5; ++d) gq[(d * 4 + c) * np + i] += cr[d] * delta;
-            q0[c] = gq[c * np + i];
-          }
-          const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
-          for (int c = 0; c < 4; ++c) gq[c * np + i] = q0[c] / nq;
-        }
-        for (int c = 0; c < 3; ++c) {
-          gr[c * np + i] = wrap(gr[c * np + i], P.L, P.invL);
-          gv[c * np + i] = gr[(1 * 3 + c) * np + i] / dt;
-        }
-      } else {
-        const double h = 0.5 * dt / D.mass;
-        for (int c = 0; c < 3; ++c) gv[c * np + i] += h * gf[c * ld + i];
-      }
-    }
-  };
-  correct(m.r, m.w, m.q, v, sd.force, sd.torque);
-  __syncthreads();
-  double k2, kr2;
-  kinetic(m, tab, sd, v, np, red, k2, kr2);
+  block_sums<5>(part, red);
+  if (threadIdx.x == 0) {
+    double* o = m.md_part + (size_t)blockIdx.x * 8;
+    for (int k = 0; k < 5; ++k) o[k] = part[k];
+  }
+}
+
+__global__ __launch_bounds__(kMdBlock) void md_thermo_kernel(SlotDev* slots, MDDev* md,
+                                                             const SysParams* __restrict__ prm) {
+  __shared__ double red[5][kMdBlock];
+  SlotDev& sd = slots[blockIdx.x];
+  MDDev& m = md[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (!m.active) {
+    // a finished slot samples nothing more (its last RDF sample was taken
+    // right after the step that ended it)
+    if (tid == 0) m.rdf_due = 0;
+    return;
+  }
+  const SysParams& P = prm[blockIdx.x];
+  // block partials: each thread a contiguous run, then the tree
+  const int nb = (sd.n + kMdBlock - 1) / kMdBlock, per = (nb + kMdBlock - 1) / kMdBlock;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = tid * per; b < min(nb, (tid + 1) * per); ++b)
+    for (int k = 0; k < 5; ++k) v[k] += m.md_part[(size_t)b * 8 + k];
+  block_sums<5>(v, red);
+  if (tid != 0) return;
+  if (hf_due(m))
+    for (int c = 0; c < 3; ++c) m.jq_now[c] = v[2 + c] + sd.jq[c];
+  double k2 = v[0], kr2 = v[1], ft = 1.0, fr = 1.0;
   if (m.temperature > 0.0) {
-    const double ft = sqrt(m.temperature * m.f_tr / k2);
-    const double fr = (m.f_rot > 0.0 && kr2 > 0.0) ? sqrt(m.temperature * m.f_rot / kr2) : 1.0;
-    auto rescale = [&](double* __restrict__ gr, double* __restrict__ gw, double* __restrict__ gq,
-                       double* __restrict__ gv) {
-      for (int i = tid; i < n; i += kMdThreads) {
-        for (int c = 0; c < 3; ++c) {
-          gv[c * np + i] *= ft;
-          if (m.integrator == MS2_GEAR) gr[(1 * 3 + c) * np + i] *= ft;
-        }
-        if (m.rotating && fr != 1.0) {
-          for (int c = 0; c < 3; ++c) gw[c * np + i] *= fr;
-          for (int c = 0; c < 4; ++c) gq[(1 * 4 + c) * np + i] *= fr;
-        }
-      }
-    };
-    rescale(m.r, m.w, m.q, v);
+    ft = sqrt(m.temperature * m.f_tr / k2);
+    fr = (m.f_rot > 0.0 && kr2 > 0.0) ? sqrt(m.temperature * m.f_rot / kr2) : 1.0;
     k2 *= ft * ft;
     kr2 *= fr * fr;
-    __syncthreads();
   }
+  m.scale_tr = ft;
+  m.scale_rot = fr;
   const long long s = m.steps_done + 1;
-  if (tid == 0) {
-    m.ekin_tr = 0.5 * k2;
-    m.ekin_rot = 0.5 * kr2;
-    const double* su = sd.sums;
-    m.pairs_total += su[MS2_SUM_NPAIR];
-    m.site_pairs_total += su[MS2_SUM_NSITE];
-    const double U = su[MS2_SUM_U_LJ] + su[MS2_SUM_U_ELEC] + su[MS2_SUM_U_RECIP] + su[MS2_SUM_U_CONST] +
-                     su[MS2_SUM_U_LRC];
-    bool ok = isfinite(U) && isfinite(k2) && isfinite(su[MS2_SUM_VIRIAL]);
-    if (m.sample_every > 0 && s % m.sample_every == 0) {
-      const double X = U - m.u0;
-      const double us = su[MS2_SUM_US] + su[MS2_SUM_US_LRC];
-      const double uss = su[MS2_SUM_USS] + su[MS2_SUM_USS_LRC];
-      const double Y = us / (3.0 * P.V);
-      const double Z = (uss - 2.0 * us) / (9.0 * P.V * P.V);
-      double* mo = m.moments;
-      mo[0] += 1.0;
-      mo[1] += X;
-      mo[2] += X * X;
-      mo[3] += X * X * X;
-      mo[4] += Y;
-      mo[5] += X * Y;
-      mo[6] += X * X * Y;
-      mo[7] += Y * Y;
-      mo[8] += X * Y * Y;
-      mo[9] += Z;
-      mo[10] += X * Z;
-    }
-    m.rdf_due = (m.rdf_every > 0 && s % m.rdf_every == 0) ? 1 : 0;
-    if (!ok) m.status = MS2_ENONFINITE;
+  m.ekin_tr = 0.5 * k2;
+  m.ekin_rot = 0.5 * kr2;
+  const double* su = sd.sums;
+  m.pairs_total += su[MS2_SUM_NPAIR];
+  m.site_pairs_total += su[MS2_SUM_NSITE];
+  const double U = su[MS2_SUM_U_LJ] + su[MS2_SUM_U_ELEC] + su[MS2_SUM_U_RECIP] + su[MS2_SUM_U_CONST] +
+                   su[MS2_SUM_U_LRC];
+  const bool ok = isfinite(U) && isfinite(k2) && isfinite(su[MS2_SUM_VIRIAL]);
+  if (m.sample_every > 0 && s % m.sample_every == 0) {
+    const double X = U - m.u0;
+    const double us = su[MS2_SUM_US] + su[MS2_SUM_US_LRC];
+    const double uss = su[MS2_SUM_USS] + su[MS2_SUM_USS_LRC];
+    const double Y = us / (3.0 * P.V);
+    const double Z = (uss - 2.0 * us) / (9.0 * P.V * P.V);
+    double* mo = m.moments;
+    mo[0] += 1.0;
+    mo[1] += X;
+    mo[2] += X * X;
+    mo[3] += X * X * X;
+    mo[4] += Y;
+    mo[5] += X * Y;
+    mo[6] += X * X * Y;
+    mo[7] += Y * Y;
+    mo[8] += X * Y * Y;
+    mo[9] += Z;
+    mo[10] += X * Z;
   }
+  m.rdf_due = (m.rdf_every > 0 && s % m.rdf_every == 0) ? 1 : 0;
+  if (!ok) m.status = MS2_ENONFINITE;
+}
+
+__global__ __launch_bounds__(kMdBlock) void md_rescale_kernel(const SlotDev* __restrict__ slots, MDDev* md) {
+  const SlotDev& sd = slots[blockIdx.y];
+  const MDDev& m = md[blockIdx.y];
+  if (!m.active || !(m.temperature > 0.0)) return;
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  if (i >= sd.n) return;
+  const int np = sd.com_ld;
+  const double ft = m.scale_tr, fr = m.scale_rot;
+  double* __restrict__ gv = m.vel;
+  double* __restrict__ gr = m.r;
+  for (int c = 0; c < 3; ++c) {
+    gv[c * np + i] *= ft;
+    if (m.integrator == MS2_GEAR) gr[(1 * 3 + c) * np + i] *= ft;
+  }
+  if (m.rotating && fr != 1.0) {
+    double* __restrict__ gw = m.w;
+    double* __restrict__ gq = m.q;
+    for (int c = 0; c < 3; ++c) gw[c * np + i] *= fr;
+    for (int c = 0; c < 4; ++c) gq[(1 * 4 + c) * np + i] *= fr;
+  }
+}
+
+__global__ __launch_bounds__(kMdThreads) void md_sample_kernel(SlotDev* slots, MDDev* md,
+                                                               const SpeciesTable* __restrict__ tab) {
+  __shared__ double red[kMdThreads];
+  SlotDev& sd = slots[blockIdx.x];
+  MDDev& m = md[blockIdx.x];
+  if (!m.active) return;
+  const int tid = threadIdx.x;
+  const long long s = m.steps_done + 1;
   if (m.acf_every > 0 && s % m.acf_every == 0) {
-    acf_sample(m, tab, sd, v, np, s, red, true);
+    acf_sample(m, tab, sd, m.vel, sd.com_ld, s, red, true);
     if (tid == 0 && m.res_on) {
       m.res_due = 1;
       m.res_step = s;
@@ -715,8 +791,12 @@ hipError_t launch_md_begin(const SlotDev* slots, MDDev* md, const SysParams* prm
 }
 
 hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const SpeciesTable* tab,
-                         int nslots, hipStream_t st) {
-  hipLaunchKernelGGL(md_end_kernel, dim3(nslots), dim3(kMdThreads), 0, st, slots, md, prm, tab);
+                         int nslots, int max_n, hipStream_t st) {
+  const int mb = (max_n + kMdBlock - 1) / kMdBlock;
+  hipLaunchKernelGGL(md_correct_kernel, dim3(mb, nslots), dim3(kMdBlock), 0, st, slots, md, prm, tab);
+  hipLaunchKernelGGL(md_thermo_kernel, dim3(nslots), dim3(kMdBlock), 0, st, slots, md, prm);
+  hipLaunchKernelGGL(md_rescale_kernel, dim3(mb, nslots), dim3(kMdBlock), 0, st, slots, md);
+  hipLaunchKernelGGL(md_sample_kernel, dim3(nslots), dim3(kMdThreads), 0, st, slots, md, tab);
   return hipGetLastError();
 }
 
