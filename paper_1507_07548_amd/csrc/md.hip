@@ -312,11 +312,13 @@ __device__ __forceinline__ bool hf_due(const MDDev& m) {
 // Gear corrector of molecule i (5-value coefficients ct for the second-order
 // translation, cr for the first-order quaternion and Euler systems; the
 // state arrays are distinct allocations, passed as restrict pointers so that
-// loads may pass stores), or the second velocity-Verlet kick
+// loads may pass stores), or the second velocity-Verlet kick.  Returns the
+// corrected velocity and (rotating Gear) body angular velocity in vo, wo.
 __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDev& D, const SysParams& P, int i,
                                                  int np, int ld, double* __restrict__ gr, double* __restrict__ gw,
                                                  double* __restrict__ gq, double* __restrict__ gv,
-                                                 const double* __restrict__ gf, const double* __restrict__ gt) {
+                                                 const double* __restrict__ gf, const double* __restrict__ gt,
+                                                 double* vo, double* wo) {
   const double dt = m.dt;
   const double ct[5] = {19.0 / 120.0, 3.0 / 4.0, 1.0, 1.0 / 2.0, 1.0 / 12.0};
   const double cr[5] = {251.0 / 720.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0};
@@ -338,7 +340,10 @@ __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDe
       quat_rate(q, w, qd);
       for (int c = 0; c < 3; ++c) {
         const double delta = dt * wd[c] - gw[(1 * 3 + c) * np + i];
-        for (int d = 0; d < 5; ++d) gw[(d * 3 + c) * np + i] += cr[d] * delta;
+        double wv[5];
+        for (int d = 0; d < 5; ++d) wv[d] = gw[(d * 3 + c) * np + i];
+        for (int d = 0; d < 5; ++d) gw[(d * 3 + c) * np + i] = wv[d] + cr[d] * delta;
+        wo[c] = wv[0] + cr[0] * delta;
       }
       double q0[4];
       for (int c = 0; c < 4; ++c) {
@@ -351,11 +356,15 @@ __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDe
     }
     for (int c = 0; c < 3; ++c) {
       gr[c * np + i] = wrap(gr[c * np + i], P.L, P.invL);
-      gv[c * np + i] = gr[(1 * 3 + c) * np + i] / dt;
+      vo[c] = gr[(1 * 3 + c) * np + i] / dt;
+      gv[c * np + i] = vo[c];
     }
   } else {
     const double h = 0.5 * dt / D.mass;
-    for (int c = 0; c < 3; ++c) gv[c * np + i] += h * gf[c * ld + i];
+    for (int c = 0; c < 3; ++c) {
+      vo[c] = gv[c * np + i] + h * gf[c * ld + i];
+      gv[c * np + i] = vo[c];
+    }
   }
 }
 
@@ -387,10 +396,13 @@ __global__ __launch_bounds__(kMdBlock) void md_correct_kernel(SlotDev* slots, MD
       e -= m.h_partial[spi];
       for (int c = 0; c < 3; ++c) part[2 + c] = e * vi[c];
     }
-    correct_molecule(m, D, P, i, np, ld, m.r, m.w, m.q, v, sd.force, sd.torque);
+    double vo[3], wo[3];
+    correct_molecule(m, D, P, i, np, ld, m.r, m.w, m.q, v, sd.force, sd.torque, vo, wo);
+    if (m.rotating && m.integrator != MS2_GEAR)
+      for (int c = 0; c < 3; ++c) wo[c] = m.w[c * np + i];
     for (int c = 0; c < 3; ++c) {
-      part[0] += D.mass * v[c * np + i] * v[c * np + i];
-      if (m.rotating) part[1] += D.inertia[c] * m.w[c * np + i] * m.w[c * np + i];
+      part[0] += D.mass * vo[c] * vo[c];
+      if (m.rotating) part[1] += D.inertia[c] * wo[c] * wo[c];
     }
   }
   block_sums<5>(part, red);
