@@ -668,57 +668,39 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
 //    tail.  OVERWRITES sums.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __restrict__ slots) {
-  // a thread sums four consecutive molecules of one force/torque component
-  // (one 16-byte load per partial in the FP32 form); the grid's x holds six
-  // runs of molecule blocks, one per component, so that the largest
+  // one thread per (component, molecule): the grid's x holds six runs of
+  // molecule blocks, one per force/torque component, so that the largest
   // systems' serial chains are one component long
   const SlotDev& sd = slots[blockIdx.y];
   if (!sd.active) return;
   const int mb = gridDim.x / 6, c = blockIdx.x / mb;
-  const int i0 = ((blockIdx.x - c * mb) * 256 + threadIdx.x) * 4;
-  if (i0 >= sd.n) return;
+  const int i = (blockIdx.x - c * mb) * 256 + threadIdx.x;
+  if (i >= sd.n) return;
   const int np = sd.npad, ld = sd.com_ld, nparts = sd.jsplits;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  // per molecule the partials are added in the order p = 0, 1, 2, ...; the
-  // loads of four partials are issued before their additions.  Lanes past
-  // n read the padding of the last tile (allocated, never stored).
-  if (sd.pf_single) {
-    const float4* pf = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(sd.pf) + (size_t)c * np + i0);
-    const size_t stride = (size_t)6 * np / 4;
-    auto add = [&](const float4& x) {
-      v[0] += (double)x.x;
-      v[1] += (double)x.y;
-      v[2] += (double)x.z;
-      v[3] += (double)x.w;
-    };
+  const size_t stride = (size_t)6 * np;
+  double v = 0.0;
+  // the loads of four partials are issued before their additions, which
+  // keep the order p = 0, 1, 2, ...
+  auto reduce = [&](auto* __restrict__ pf) {
     int p = 0;
     for (; p + 4 <= nparts; p += 4) {
-      const float4 x0 = pf[(size_t)p * stride], x1 = pf[(size_t)(p + 1) * stride];
-      const float4 x2 = pf[(size_t)(p + 2) * stride], x3 = pf[(size_t)(p + 3) * stride];
-      add(x0);
-      add(x1);
-      add(x2);
-      add(x3);
+      const double x0 = (double)pf[(size_t)p * stride], x1 = (double)pf[(size_t)(p + 1) * stride];
+      const double x2 = (double)pf[(size_t)(p + 2) * stride], x3 = (double)pf[(size_t)(p + 3) * stride];
+      v += x0;
+      v += x1;
+      v += x2;
+      v += x3;
     }
-    for (; p < nparts; ++p) add(pf[(size_t)p * stride]);
-  } else {
-    const double2* pf = reinterpret_cast<const double2*>(reinterpret_cast<const double*>(sd.pf) + (size_t)c * np + i0);
-    const size_t stride = (size_t)6 * np / 2;
-    int p = 0;
-    for (; p + 2 <= nparts; p += 2) {
-      const double2 a0 = pf[(size_t)p * stride], a1 = pf[(size_t)p * stride + 1];
-      const double2 b0 = pf[(size_t)(p + 1) * stride], b1 = pf[(size_t)(p + 1) * stride + 1];
-      v[0] += a0.x; v[1] += a0.y; v[2] += a1.x; v[3] += a1.y;
-      v[0] += b0.x; v[1] += b0.y; v[2] += b1.x; v[3] += b1.y;
-    }
-    for (; p < nparts; ++p) {
-      const double2 a0 = pf[(size_t)p * stride], a1 = pf[(size_t)p * stride + 1];
-      v[0] += a0.x; v[1] += a0.y; v[2] += a1.x; v[3] += a1.y;
-    }
-  }
-  double* out = c < 3 ? sd.force + (size_t)c * ld : sd.torque + (size_t)(c - 3) * ld;
-  for (int k = 0; k < 4; ++k)
-    if (i0 + k < sd.n) out[i0 + k] = v[k];
+    for (; p < nparts; ++p) v += (double)pf[(size_t)p * stride];
+  };
+  if (sd.pf_single)
+    reduce(reinterpret_cast<const float*>(sd.pf) + (size_t)c * np + i);
+  else
+    reduce(reinterpret_cast<const double*>(sd.pf) + (size_t)c * np + i);
+  if (c < 3)
+    sd.force[c * ld + i] = v;
+  else
+    sd.torque[(c - 3) * ld + i] = v;
 }
 
 __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restrict__ slots,
@@ -884,7 +866,7 @@ hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool s
 
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_force_kernel, dim3(6 * ((max_n + 1023) / 1024), nslots), dim3(256), 0, st, slots);
+  hipLaunchKernelGGL(reduce_force_kernel, dim3(6 * ((max_n + 255) / 256), nslots), dim3(256), 0, st, slots);
   hipLaunchKernelGGL(reduce_sums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();
 }
