@@ -1,0 +1,101 @@
+"""Host logic behind the bench line's measured fields: the rocprofv3 summary
+tool (trace tables, counter averages, HBM bytes scaled by a copy of known
+size) and bench.recorded_traffic(), which reports traffic only while the pair
+kernel sources hash to the recorded value.  Synthetic trace databases and
+counter files stand in for rocprofv3 output."""
+import csv
+import os
+import sqlite3
+
+import pytest
+
+import bench
+from paper_1507_07548_amd import rocprof_summary as R
+
+
+def kernel_db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table kernels (name text, grid_x int, grid_y int, grid_z int, duration int)")
+    con.executemany("insert into kernels values (?, ?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    return path
+
+
+def counter_csv(path, counter, dispatches):
+    """dispatches: (dispatch id, kernel name, grid size, value); each value is
+    split over two rows, as rocprofv3 reports one row per agent instance."""
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, name, grid, value in dispatches:
+            for part in (0.25 * value, 0.75 * value):
+                w.writerow({"Dispatch_Id": d, "Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter,
+                            "Counter_Value": part})
+    return path
+
+
+SYM = "void ms2::pair_sym_kernel<float, 1, false, false, true>(ms2::WorkItem const*, int)"
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def test_trace_tables(tmp_path):
+    db = kernel_db(str(tmp_path / "k.db"), [
+        (SYM, 1000, 1, 1, 4_000_000), (SYM, 1000, 1, 1, 5_000_000),    # two batched launches
+        (SYM, 10, 1, 1, 50_000),                                       # a small launch
+        ("ms2::md_correct_kernel(int)", 256, 4, 1, 100_000),
+    ])
+    table = R.summarize(db)
+    assert table.splitlines()[2].startswith("| `void ms2::pair_sym_kernel<float, 1, false, false, true>` | 3 |")
+    n, avg_us, grid = R.largest_grid(db, "pair_sym_kernel<float")
+    assert (n, grid) == (2, 1000) and avg_us == pytest.approx(4500.0)
+    sel = R.select(db, ["md_correct", "nothing"]).splitlines()
+    assert len(sel) == 3 and "| 1024 | 1 | 100.0 | 0.10 |" in sel[2]
+    with pytest.raises(SystemExit):
+        R.largest_grid(db, "absent_kernel")
+
+
+def test_counters_average_the_largest_grid(tmp_path):
+    f = counter_csv(str(tmp_path / "c.csv"), "SQ_INSTS_VALU",
+                    [(1, SYM, 1000, 300.0), (2, SYM, 1000, 500.0), (3, SYM, 8, 7.0)])
+    out = R.counters(f, "pair_sym_kernel<float")
+    assert "2 launches of grid 1000" in out and "| SQ_INSTS_VALU | 400 |" in out
+
+
+def test_traffic_scales_each_counter_by_the_copy(tmp_path, monkeypatch):
+    gib = 1 << 30
+    # the copy of 1 GiB reads as 0.5 GiB of FETCH_SIZE and 1 GiB of WRITE_SIZE
+    fetch = counter_csv(str(tmp_path / "f.csv"), "FETCH_SIZE",
+                        [(1, COPY, 4096, gib / 2 / 1024), (2, SYM, 1000, 1000.0), (3, SYM, 1000, 3000.0)])
+    write = counter_csv(str(tmp_path / "w.csv"), "WRITE_SIZE",
+                        [(1, COPY, 4096, gib / 1024), (2, SYM, 1000, 500.0), (3, SYM, 1000, 500.0)])
+    text = R.traffic(fetch, write, gib, "pair_sym_kernel<float")
+    # FETCH: 2000 KiB-units x 2048 B; WRITE: 500 x 1024 B
+    assert "- hbm_bytes_per_launch: 4.608e+06" in text
+    summary = tmp_path / "summary.md"
+    summary.write_text("# traffic\n\n" + text + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
+    assert bench.recorded_traffic() == pytest.approx(4.608e6)
+    # a change of the pair kernel sources voids the record
+    monkeypatch.setattr(R, "pair_kernel_source_hash", lambda: "0" * 64)
+    assert bench.recorded_traffic() is None
+    with pytest.raises(SystemExit):          # no copy of known size in the run
+        R.traffic(counter_csv(str(tmp_path / "g.csv"), "FETCH_SIZE", [(2, SYM, 1000, 1.0)]), write, gib,
+                  "pair_sym_kernel<float")
+
+
+def test_source_hash_follows_every_pair_kernel_file(tmp_path, monkeypatch):
+    for rel in R.PAIR_SOURCES:
+        dst = tmp_path / rel
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        dst.write_bytes(open(os.path.join(R.HERE, rel), "rb").read())
+    monkeypatch.setattr(R, "HERE", str(tmp_path))
+    base = R.pair_kernel_source_hash()
+    assert len(base) == 64
+    for rel in R.PAIR_SOURCES:
+        f = tmp_path / rel
+        orig = f.read_bytes()
+        f.write_bytes(orig + b" ")
+        assert R.pair_kernel_source_hash() != base, rel
+        f.write_bytes(orig)
+    assert R.pair_kernel_source_hash() == base
