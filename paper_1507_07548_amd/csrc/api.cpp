@@ -420,7 +420,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   }
   const int mchunks = (n + kMolTile - 1) / kMolTile;
   const int kchunks = (nk + kKChunk - 1) / kKChunk;
-  const int mtiles = (n + 63) / 64;
+  const int mtiles = (n + kMolTile - 1) / kMolTile;
   MS2_HIP(ctx->s_sites.ensure((size_t)class_reals(ctx->cls) * npad * rs));
   MS2_HIP(ctx->s_pf.ensure((size_t)js * 6 * npad * 8));
   MS2_HIP(ctx->s_bsum.ensure((size_t)nitems * kNumBlockSums * 8));

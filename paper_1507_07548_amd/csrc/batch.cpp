@@ -241,7 +241,7 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
     s.nk = kvec_count(sys->params.kmax2);
     s.kchunks = (s.nk + kKChunk - 1) / kKChunk;
     s.mchunks = (s.n + kMolTile - 1) / kMolTile;
-    s.mtiles = (s.n + 63) / 64;
+    s.mtiles = (s.n + kMolTile - 1) / kMolTile;
   }
   if (sys->rdf_every > 0) {
     if (sys->rdf_bins < 1 || !(sys->rdf_rmax > 0.0))

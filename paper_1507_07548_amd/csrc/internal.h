@@ -19,7 +19,7 @@ constexpr int kNumBlockSums = 9;  // u_lj, u_el, us, uss, npair, nsite, J_q pair
 // Ewald blocks are single waves running long FP64 chains: short chunks give
 // small systems enough waves in flight.
 constexpr int kKChunk = 32;       // k vectors per reciprocal-force block
-constexpr int kMolTile = 16;      // molecules per structure-factor block (one wave of 64 k)
+constexpr int kMolTile = 16;      // molecules per structure-factor block (16 x 4 charge slots = one wave)
 constexpr int kMaxRdfTypes = 16;
 
 // Model classes: compile-time upper bounds on the sites of each type per
@@ -113,7 +113,7 @@ struct SlotDev {
   double* kred;               // [kchunks][kblocks_m] sum_a d_a . F_a partials + [2] U, W_atomic
   double* ksum;               // [4]: U_recip, W_atomic, sum d.F, spare
   const struct KVec* kvec;    // [nk] half-space integer vectors
-  int nk, mtiles;             // k vectors; 64-molecule tiles of the force kernel
+  int nk, mtiles;             // k vectors; kMolTile-molecule tiles of the reciprocal-force kernel
 };
 
 // Species indices come from caller memory: clamp them into the table so a

@@ -4,10 +4,11 @@
 // phases are reduced to [-pi, pi] exactly via the integer period of the k
 // lattice, and S(k) is accumulated in FP64.
 //
-//   sk_kernel          (k block of 64) x (molecule tile): partial S(k)
+//   sk_kernel          (k block of 64) x (16-molecule tile): partial S(k),
+//                      phases carried along the k lines per charge
 //   sk_reduce_kernel   64 k per block: S(k) over tiles in fixed order and
 //                      the k's energy and atomic-virial terms
-//   kforce_kernel      (64-molecule tile) x (k chunk): per-molecule force,
+//   kforce_kernel      (16-molecule tile) x (k chunk): per-molecule force,
 //                      torque and sum d.F partials
 //   reduce_kforce_kernel, reduce_ksums_kernel: add the force partials and the
 //                      per-k terms (fixed order) into the caller's force,
@@ -42,56 +43,103 @@ __device__ __forceinline__ void phase(double t, double& c, double& s) {
   sincospi(2.0 * t, &s, &c);
 }
 
+// Partial S(k) of one tile of kMolTile = 16 molecules for 64 k vectors.  A
+// block is one wave; lane l owns charge l mod 4 of molecule l / 4 of the
+// tile (every model class has at most four charges per molecule) and carries
+// its phase exp(2 pi i n.r / L) from k to k: inside a line of the k set
+// (n_x, n_y fixed, n_z rising by one) by one complex product with
+// exp(2 pi i z / L), from sincospi at a line's or the block's first k.
+// Batches of 8 k go through LDS: lane l adds the 8 charges of segment l / 8
+// for the k l mod 8 of the batch, and the eight segment sums are added in
+// segment order (8 KB of LDS per block, so that ~4 waves per SIMD fit).
+constexpr int kChargeSlots = 4;
+static_assert(kMolTile * kChargeSlots == 64, "one charge slot per lane");
+
 __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slots,
                                                 const SysParams* __restrict__ prm,
                                                 const SpeciesTable* __restrict__ tab) {
-  __shared__ double s_x[kMolTile * kMaxS], s_y[kMolTile * kMaxS], s_z[kMolTile * kMaxS],
-      s_q[kMolTile * kMaxS];
+  __shared__ double2 s_c[8][65];        // q exp(i k.r) per (k of the batch, lane); padded rows
+  __shared__ double2 s_seg[8][8];
+  __shared__ int s_n[64][3];
+  __shared__ int s_next[64];            // 1: k continues the line of the previous k
   const SlotDev& sd = slots[blockIdx.z];
   const SysParams& P = prm[blockIdx.z];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
   const int mc = blockIdx.y;
   if (mc >= sd.mchunks || (int)blockIdx.x * 64 >= sd.nk) return;
-  const int tid = threadIdx.x, ld = sd.com_ld;
-  const int m0 = mc * kMolTile, m1 = min(sd.n, m0 + kMolTile);
-  int maxq = 0;
-  for (int s = 0; s < P.nsp; ++s) maxq = max(maxq, tab->sp[s].nch);
-  if (tid < kMolTile) {
-    const int i = m0 + tid;
-    for (int a = 0; a < maxq; ++a) s_q[tid * kMaxS + a] = 0.0;
-    if (i < m1) {
-      const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], P.nsp)];
+  const int lane = threadIdx.x, ld = sd.com_ld;
+  const int k0 = blockIdx.x * 64, nkb = min(64, sd.nk - k0);
+  if (lane < nkb) {
+    const KVec kv = sd.kvec[k0 + lane];
+    s_n[lane][0] = kv.nx;
+    s_n[lane][1] = kv.ny;
+    s_n[lane][2] = kv.nz;
+    int next = 0;
+    if (lane > 0) {
+      const KVec kp = sd.kvec[k0 + lane - 1];
+      next = kp.nx == kv.nx && kp.ny == kv.ny && kp.nz + 1 == kv.nz;
+    }
+    s_next[lane] = next;
+  }
+  const int i = mc * kMolTile + (lane >> 2), a = lane & (kChargeSlots - 1);
+  double q = 0.0, x = 0.0, y = 0.0, z = 0.0;
+  if (i < sd.n) {
+    const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], P.nsp)];
+    if (a < min(D.nch, kChargeSlots)) {
       double A[3][3];
       quat_rot(sd.quat, ld, i, A);
-      const double cx = sd.com[i], cy = sd.com[ld + i], cz = sd.com[2 * ld + i];
-      for (int a = 0; a < D.nch; ++a) {
-        const double* b = D.ch_pos[a];
-        s_x[tid * kMaxS + a] = cx + A[0][0] * b[0] + A[0][1] * b[1] + A[0][2] * b[2];
-        s_y[tid * kMaxS + a] = cy + A[1][0] * b[0] + A[1][1] * b[1] + A[1][2] * b[2];
-        s_z[tid * kMaxS + a] = cz + A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2];
-        s_q[tid * kMaxS + a] = D.ch_q[a];
-      }
+      const double* b = D.ch_pos[a];
+      x = sd.com[i] + A[0][0] * b[0] + A[0][1] * b[1] + A[0][2] * b[2];
+      y = sd.com[ld + i] + A[1][0] * b[0] + A[1][1] * b[1] + A[1][2] * b[2];
+      z = sd.com[2 * ld + i] + A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2];
+      q = D.ch_q[a];
     }
   }
   __syncthreads();
-  const int k = blockIdx.x * 64 + tid;
-  if (k >= sd.nk) return;
-  const KVec kv = sd.kvec[k];
   const double invL = P.invL;
-  double re = 0.0, im = 0.0;
-  for (int m = 0; m < m1 - m0; ++m)
-    for (int a = 0; a < maxq; ++a) {
-      const int e = m * kMaxS + a;
-      const double q = s_q[e];
-      if (q == 0.0) continue;
-      double c, s;
-      phase((kv.nx * s_x[e] + kv.ny * s_y[e] + kv.nz * s_z[e]) * invL, c, s);
-      re += q * c;
-      im += q * s;
+  double ezc, ezs;
+  phase(z * invL, ezc, ezs);
+  double c = 1.0, s = 0.0;
+  double* out = sd.sk_part + ((size_t)mc * sd.nk + k0) * 2;
+  for (int b0 = 0; b0 < nkb; b0 += 8) {
+    for (int j = 0; j < 8; ++j) {
+      const int e = b0 + j;
+      double2 v = make_double2(0.0, 0.0);
+      if (e < nkb) {
+        if (s_next[e]) {
+          const double c1 = c * ezc - s * ezs;
+          s = c * ezs + s * ezc;
+          c = c1;
+        } else {
+          phase((s_n[e][0] * x + s_n[e][1] * y + s_n[e][2] * z) * invL, c, s);
+        }
+        v = make_double2(q * c, q * s);
+      }
+      s_c[j][lane] = v;
     }
-  double* out = sd.sk_part + ((size_t)mc * sd.nk + k) * 2;
-  out[0] = re;
-  out[1] = im;
+    __syncthreads();
+    {
+      const int j = lane & 7, seg = lane >> 3;
+      double re = 0.0, im = 0.0;
+      for (int t = 0; t < 8; ++t) {
+        const double2 v = s_c[j][8 * seg + t];
+        re += v.x;
+        im += v.y;
+      }
+      s_seg[seg][j] = make_double2(re, im);
+    }
+    __syncthreads();
+    if (lane < 8 && b0 + lane < nkb) {
+      double re = s_seg[0][lane].x, im = s_seg[0][lane].y;
+      for (int g = 1; g < 8; ++g) {
+        re += s_seg[g][lane].x;
+        im += s_seg[g][lane].y;
+      }
+      out[2 * (b0 + lane)] = re;
+      out[2 * (b0 + lane) + 1] = im;
+    }
+    __syncthreads();
+  }
 }
 
 // S(k) summed over the molecule tiles in a fixed order: a block holds 64 k,
@@ -146,13 +194,21 @@ __global__ __launch_bounds__(256) void sk_reduce_kernel(const SlotDev* __restric
   sd.sk_part[2 * k + 1] = g * s2 * (1.0 - k2 / (2.0 * P.alpha2));
 }
 
+// Reciprocal forces: a block is one wave over a tile of kMolTile molecules
+// and a chunk of kKChunk k vectors; lane l owns charge l mod 4 of molecule
+// l / 4 and walks the chunk with its phase carried along the n_z lines (one
+// complex product per k, sincospi at a line's or the chunk's first k).  Each
+// molecule's force, torque and d.F are the sums of its four slots in charge
+// order; lane 4m writes them.
 __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ slots,
                                                     const SysParams* __restrict__ prm,
                                                     const SpeciesTable* __restrict__ tab) {
-  __shared__ double s_re[kKChunk], s_im[kKChunk], s_g[kKChunk];
-  __shared__ int s_n[kKChunk][3];
-  __shared__ int s_next[kKChunk];   // 1: k is k - 1 of the chunk plus one step in n_z
-  __shared__ double s_red[64];
+  // per k: (g(k) Re S(k), g(k) Im S(k)) and (n_x, n_y, n_z, 1 if k continues the
+  // previous k's line else 0), as doubles: two 16-byte LDS reads per k
+  __shared__ double2 s_gs[kKChunk];
+  __shared__ double4 s_nk[kKChunk];
+  __shared__ double s_v[7][64];     // per slot: force, torque, d.F
+  __shared__ double s_red[kMolTile];
   const SlotDev& sd = slots[blockIdx.z];
   const SysParams& P = prm[blockIdx.z];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
@@ -163,78 +219,80 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
   const double k2s = (kTwoPi * P.invL) * (kTwoPi * P.invL);
   for (int e = tid; e < nkc; e += 64) {
     const KVec kv = sd.kvec[k0 + e];
-    s_re[e] = sd.sk[2 * (k0 + e)];
-    s_im[e] = sd.sk[2 * (k0 + e) + 1];
     const double k2 = k2s * kv.n2;
-    s_g[e] = exp(-k2 / (4.0 * P.alpha2)) / k2;
-    s_n[e][0] = kv.nx;
-    s_n[e][1] = kv.ny;
-    s_n[e][2] = kv.nz;
+    const double g = exp(-k2 / (4.0 * P.alpha2)) / k2;
+    s_gs[e] = make_double2(g * sd.sk[2 * (k0 + e)], g * sd.sk[2 * (k0 + e) + 1]);
     int next = 0;
     if (e > 0) {
       const KVec kp = sd.kvec[k0 + e - 1];
       next = kp.nx == kv.nx && kp.ny == kv.ny && kp.nz + 1 == kv.nz;
     }
-    s_next[e] = next;
+    s_nk[e] = make_double4(kv.nx, kv.ny, kv.nz, next);
   }
   __syncthreads();
-  const int i = blockIdx.x * 64 + tid;
-  double dF = 0.0;
+  const int mloc = tid >> 2, a = tid & (kChargeSlots - 1);
+  const int i = blockIdx.x * kMolTile + mloc;
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // F, tau, d.F of this slot's charge
   if (i < sd.n) {
     const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], P.nsp)];
-    double A[3][3];
-    quat_rot(sd.quat, ld, i, A);
-    const double cx = sd.com[i], cy = sd.com[ld + i], cz = sd.com[2 * ld + i];
-    double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-    // F_a = (4 pi k_e q_a / V) sum_k g(k) k Im(e^{i k.r_a} S(k)^*), doubled
-    const double pre = 2.0 * P.ke * 4.0 * kPi / P.V;
-    for (int a = 0; a < D.nch; ++a) {
+    if (a < min(D.nch, kChargeSlots)) {
+      double A[3][3];
+      quat_rot(sd.quat, ld, i, A);
       const double* b = D.ch_pos[a];
       const double d[3] = {A[0][0] * b[0] + A[0][1] * b[1] + A[0][2] * b[2],
                            A[1][0] * b[0] + A[1][1] * b[1] + A[1][2] * b[2],
                            A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2]};
-      const double x = cx + d[0], y = cy + d[1], z = cz + d[2];
+      const double x = sd.com[i] + d[0], y = sd.com[ld + i] + d[1], z = sd.com[2 * ld + i] + d[2];
+      // F_a = (4 pi k_e q_a / V) sum_k g(k) k Im(e^{i k.r_a} S(k)^*), doubled
       double sx = 0.0, sy = 0.0, sz = 0.0;
-      // along a line of the k set (n_x, n_y fixed, n_z rising by one) the
-      // phase advances by exp(i 2 pi z / L): one complex product; a line's
-      // first k takes the phase directly
       double ezc, ezs;
       phase(z * P.invL, ezc, ezs);
       double c = 1.0, s = 0.0;
       for (int e = 0; e < nkc; ++e) {
-        if (s_next[e]) {
+        const double4 nk = s_nk[e];
+        const double2 gs = s_gs[e];
+        if (nk.w != 0.0) {
           const double c1 = c * ezc - s * ezs;
           s = c * ezs + s * ezc;
           c = c1;
         } else {
-          phase((s_n[e][0] * x + s_n[e][1] * y + s_n[e][2] * z) * P.invL, c, s);
+          phase((nk.x * x + nk.y * y + nk.z * z) * P.invL, c, s);
         }
-        const double t = s_g[e] * (s * s_re[e] - c * s_im[e]);
-        sx += t * s_n[e][0];
-        sy += t * s_n[e][1];
-        sz += t * s_n[e][2];
+        const double t = s * gs.x - c * gs.y;
+        sx += t * nk.x;
+        sy += t * nk.y;
+        sz += t * nk.z;
       }
+      const double pre = 2.0 * P.ke * 4.0 * kPi / P.V;
       const double f = pre * D.ch_q[a] * kTwoPi * P.invL;
       const double fa[3] = {f * sx, f * sy, f * sz};
-      F[0] += fa[0]; F[1] += fa[1]; F[2] += fa[2];
-      T[0] += d[1] * fa[2] - d[2] * fa[1];
-      T[1] += d[2] * fa[0] - d[0] * fa[2];
-      T[2] += d[0] * fa[1] - d[1] * fa[0];
-      dF += d[0] * fa[0] + d[1] * fa[1] + d[2] * fa[2];
-    }
-    double* out = sd.fk + (size_t)kc * 6 * np;
-    for (int c = 0; c < 3; ++c) {
-      out[c * np + i] = F[c];
-      out[(3 + c) * np + i] = T[c];
+      v[0] = fa[0];
+      v[1] = fa[1];
+      v[2] = fa[2];
+      v[3] = d[1] * fa[2] - d[2] * fa[1];
+      v[4] = d[2] * fa[0] - d[0] * fa[2];
+      v[5] = d[0] * fa[1] - d[1] * fa[0];
+      v[6] = d[0] * fa[0] + d[1] * fa[1] + d[2] * fa[2];
     }
   }
-  s_red[tid] = dF;
+  for (int k = 0; k < 7; ++k) s_v[k][tid] = v[k];
   __syncthreads();
-  for (int h = 32; h > 0; h >>= 1) {
-    if (tid < h) s_red[tid] += s_red[tid + h];
-    __syncthreads();
+  if (a == 0) {
+    double w[7];
+    for (int k = 0; k < 7; ++k)
+      w[k] = ((s_v[k][tid] + s_v[k][tid + 1]) + s_v[k][tid + 2]) + s_v[k][tid + 3];
+    if (i < sd.n) {
+      double* out = sd.fk + (size_t)kc * 6 * np;
+      for (int c = 0; c < 6; ++c) out[c * np + i] = w[c];
+    }
+    s_red[mloc] = w[6];
   }
-  if (tid == 0) sd.kred[(size_t)kc * sd.mtiles + blockIdx.x] = s_red[0];
+  __syncthreads();
+  if (tid == 0) {
+    double dF = 0.0;
+    for (int m = 0; m < kMolTile; ++m) dF += s_red[m];
+    sd.kred[(size_t)kc * sd.mtiles + blockIdx.x] = dF;
+  }
 }
 
 // One thread per (component, molecule): the grid's x holds six runs of
@@ -281,7 +339,18 @@ __global__ __launch_bounds__(256) void reduce_ksums_kernel(const SlotDev* __rest
   const int nr = sd.kchunks * sd.mtiles;
   const int per = (nr + 255) / 256;
   double d = 0.0;
-  for (int t = tid * per; t < min(nr, (tid + 1) * per); ++t) d += sd.kred[t];
+  {
+    const int t1 = min(nr, (tid + 1) * per);
+    int t = tid * per;
+    for (; t + 4 <= t1; t += 4) {            // four loads before their additions, same order
+      const double x0 = sd.kred[t], x1 = sd.kred[t + 1], x2 = sd.kred[t + 2], x3 = sd.kred[t + 3];
+      d += x0;
+      d += x1;
+      d += x2;
+      d += x3;
+    }
+    for (; t < t1; ++t) d += sd.kred[t];
+  }
   const int perk = (sd.nk + 255) / 256;
   double u = 0.0, w = 0.0;
   for (int k = tid * perk; k < min(sd.nk, (tid + 1) * perk); ++k) {
@@ -320,8 +389,8 @@ hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const Speci
   hipLaunchKernelGGL(sk_reduce_kernel, dim3(max_kblocks, nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
-  hipLaunchKernelGGL(reduce_kforce_kernel, dim3(6 * ((64 * max_mtiles + 255) / 256), nslots), dim3(256), 0,
-                     st, slots, prm);
+  hipLaunchKernelGGL(reduce_kforce_kernel, dim3(6 * ((kMolTile * max_mtiles + 255) / 256), nslots), dim3(256),
+                     0, st, slots, prm);
   hipLaunchKernelGGL(reduce_ksums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();
 }
