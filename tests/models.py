@@ -39,6 +39,19 @@ def ionic_pair_species():
     ]
 
 
+def four_charge_species() -> Species:
+    """Neutral rigid molecule with four off-centre charges (the most any model
+    class carries) around one LJ site: every charge slot of the reciprocal
+    kernels in use."""
+    return Species("TETRA4", [
+        Site(LJ, (0.0, 0.0, 0.0), sigma=1.0, eps=1.0),
+        Site(CHARGE, (0.25, 0.25, 0.25), mag=0.6),
+        Site(CHARGE, (-0.25, -0.25, 0.25), mag=0.4),
+        Site(CHARGE, (-0.25, 0.25, -0.25), mag=-0.7),
+        Site(CHARGE, (0.25, -0.25, -0.25), mag=-0.3),
+    ], 1.0, (0.05, 0.05, 0.05))
+
+
 def small_system(species, n, box, rc, seed, elec=ELEC_NONE, jitter=0.15, **pkw):
     """n molecules on a jittered simple-cubic lattice with random orientations
     and random species assignment."""

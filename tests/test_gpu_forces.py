@@ -27,7 +27,7 @@ import numpy as np
 import pytest
 
 import oracle
-from models import ionic_pair_species, offset_multipoles, small_system
+from models import four_charge_species, ionic_pair_species, offset_multipoles, small_system
 from paper_1507_07548_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -194,6 +194,21 @@ def test_ewald_mixture_ragged(n, shape):
                      alpha=6.0 / box, kmax2=30)
     for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
         f, t, su, fo, to, so, ef, et = compare(s, prec, label="ewald mixture", shape=shape)
+        assert ef < tol and et < tol, (ef, et)
+        assert abs(su[2] - so[2]) <= 1e-10 * abs(so[2])
+
+
+@pytest.mark.parametrize("n", [37, 130])
+def test_ewald_four_charge_molecules(n):
+    """Four charges per molecule with ions: every charge slot of the reciprocal
+    kernels (16 molecules x 4 slots per wave), tiles of 16 left ragged."""
+    box = 1.3 * n ** (1 / 3) + 3.0
+    ions = ionic_pair_species()[:2]
+    s = small_system([four_charge_species()] + ions, n, box, 0.45 * box, seed=n + 1, elec=I.ELEC_EWALD,
+                     alpha=6.0 / box, kmax2=30)
+    assert (np.asarray(s.species_idx) == 0).sum() > n // 4
+    for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 2e-5)]:
+        f, t, su, fo, to, so, ef, et = compare(s, prec, label="ewald four charges")
         assert ef < tol and et < tol, (ef, et)
         assert abs(su[2] - so[2]) <= 1e-10 * abs(so[2])
 
