@@ -1,8 +1,10 @@
 // Ewald reciprocal space on gfx950 (the paper's Sec. 4: the long-range part
 // of the Coulomb sum is done in Fourier space).  Everything here is FP64:
-// charge positions are rebuilt from the centre and the quaternion in FP64,
-// phases are reduced to [-pi, pi] exactly via the integer period of the k
-// lattice, and S(k) is accumulated in FP64.
+// charge positions are rebuilt from the centre and the quaternion in FP64;
+// a charge's phase is taken from sincospi (its argument reduced by the
+// nearest integer first, exact for the integer k lattice) at the first k of
+// each line of the k set and carried along the line by complex products;
+// S(k) is accumulated in FP64.
 //
 //   sk_kernel          (k block of 64) x (16-molecule tile): partial S(k),
 //                      phases carried along the k lines per charge
@@ -54,6 +56,13 @@ __device__ __forceinline__ void phase(double t, double& c, double& s) {
 // segment order (8 KB of LDS per block, so that ~4 waves per SIMD fit).
 constexpr int kChargeSlots = 4;
 static_assert(kMolTile * kChargeSlots == 64, "one charge slot per lane");
+
+constexpr int max_class_charges() {
+  int m = 0;
+  for (int c = 0; c < kNumClasses; ++c) m = kClassShapes[c].ch > m ? kClassShapes[c].ch : m;
+  return m;
+}
+static_assert(max_class_charges() <= kChargeSlots, "every charge of every model class needs a slot");
 
 __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slots,
                                                 const SysParams* __restrict__ prm,
