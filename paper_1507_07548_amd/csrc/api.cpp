@@ -328,6 +328,14 @@ TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
   return c;
 }
 
+bool single_species_form(const ms2_ctx* ctx) {
+  if (ctx->tab.nsp != 1) return false;
+  const SpeciesDev& d = ctx->tab.sp[0];
+  const ClassShape& S = kClassShapes[ctx->cls];
+  return (S.lj == 0 || d.nlj >= 1) && (S.ch == 0 || d.nch >= 1) && (S.dp == 0 || d.ndp >= 1) &&
+         (S.qd == 0 || d.nqd >= 1);
+}
+
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits) {
   if (c.waves == 0) {  // symmetric: tile pairs (I, J >= I) of 64 molecules
     const int nt = (n + 63) / 64;
@@ -562,7 +570,7 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
   const ms2::CachedItems& ci = ctx->item_cache[std::make_tuple(n_mol, cfg.waves, cfg.jchunk)];
   MS2_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n_mol, st));
   MS2_HIP(launch_pair(ctx->cls, h_params->precision, cfg.waves, false, h_params->cutoff_mode == MS2_CUT_SITE,
-                      ctx->tab.nsp == 1, (const WorkItem*)ci.buf.p, 0, nitems,
+                      single_species_form(ctx), (const WorkItem*)ci.buf.p, 0, nitems,
                       r->d_slot, r->d_prm, ctx->d_tab, st));
   MS2_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, n_mol, st));
   MS2_HIP(hipEventRecord(r->ev, st));

@@ -348,7 +348,7 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
   }
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_begin[timed_step], st));
   for (auto& g : b->groups)
-    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, ctx->tab.nsp == 1, di, g.begin,
+    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, single_species_form(ctx), di, g.begin,
                         g.end - g.begin, ds, dp, ctx->d_tab, st));
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
   MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));

@@ -67,4 +67,7 @@ ms2_status kvec_table(ms2_ctx* ctx, int kmax2, const KVec** d_out, int* nk);
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n);
 int size_bucket(int n);
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits);
+// true when the pair kernels may take their single-species form: one species,
+// with at least one site of every kind its model class holds
+bool single_species_form(const ms2_ctx* ctx);
 }  // namespace ms2

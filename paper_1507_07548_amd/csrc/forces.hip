@@ -370,8 +370,10 @@ struct SymFinal {
 template <typename Real, int C, bool HF, bool SITE>
 constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6 : 1;
 
-// ONE: every molecule of the system is species 0 (instantiated for classes
-// 0-3); the species reads and table indexing drop out.
+// ONE: every molecule of the system is species 0, a species with at least
+// one site of every kind its class holds (instantiated for classes 0-3); the
+// species reads and table indexing drop out, and the first site pair of each
+// kind starts its sums.
 template <typename Real, int C, bool HF, bool SITE, bool ONE>
 __global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(kSymOccupancy<Real, C, HF, SITE>)))
 void pair_sym_kernel(const WorkItem* __restrict__ items,

@@ -338,6 +338,15 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
   };
   const int nlj_i = count(spi, 0), nch_i = count(spi, 1), ndp_i = count(spi, 2), nqd_i = count(spi, 3);
   const int nlj_j = count(spj, 0), nch_j = count(spj, 1), ndp_j = count(spj, 2), nqd_j = count(spj, 3);
+  if constexpr (ONE) {
+    // the single-species form is taken only for a species with at least one
+    // site of every kind its class holds: the first site pair of each kind
+    // always runs, so its sums start from it instead of from -0
+    if constexpr (S.lj > 0) __builtin_assume(nlj_i >= 1 && nlj_j >= 1);
+    if constexpr (S.ch > 0) __builtin_assume(nch_i >= 1 && nch_j >= 1);
+    if constexpr (S.dp > 0) __builtin_assume(ndp_i >= 1 && ndp_j >= 1);
+    if constexpr (S.qd > 0) __builtin_assume(nqd_i >= 1 && nqd_j >= 1);
+  }
   auto J = [&](int k) { return sj[k * STRIDE]; };
 
   // Lennard-Jones site pairs
