@@ -368,7 +368,9 @@ struct SymFinal {
 // without spilling, and the kernel hides its LDS latency better with six
 // waves than with five); the compiler's choice otherwise.
 template <typename Real, int C, bool HF, bool SITE>
-constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6 : 1;
+constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6
+                              : (sizeof(Real) == 8 && C == 1 && !HF && !SITE) ? 4
+                                                                             : 1;
 
 // ONE: every molecule of the system is species 0, a species with at least
 // one site of every kind its class holds (instantiated for classes 0-3); the
@@ -388,8 +390,8 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     SymTiles<Real, NR, HF> t;
     SymFinal<Real> f;
   } u;
-  __shared__ int s_sp[2][TJ];
-  __shared__ PairTables<Real, C> s_tab;
+  __shared__ int s_sp[ONE ? 1 : 2][ONE ? 1 : TJ];   // species of rows, columns (not read when ONE)
+  __shared__ PairTables<Real, C, ONE ? 1 : kMaxSp> s_tab;
   __shared__ unsigned s_mpart[NW][TJ];
   __shared__ unsigned long long s_dw[TJ];
   __shared__ int s_list[NW][TJ];          // per wave: row | diagonal << 6 of each entry of the chunk
@@ -432,7 +434,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
         (side ? u.t.comj : u.t.comi)[c][lane] = c3[c];
         in = in && c3[c] >= 0.0 && c3[c] <= L;
       }
-      s_sp[side][lane] = sp;
+      if constexpr (!ONE) s_sp[side][lane] = sp;
       const bool all_in = __builtin_amdgcn_ballot_w64(!in) == 0ull;
       if (lane == 0) s_inbox[side] = all_in ? 1 : 0;
     } else {

@@ -266,23 +266,26 @@ struct SiteAcc {
   }
 };
 
-// LDS tables of the species of one system, as the pair kernels stage them.
-template <typename Real, int C>
+// LDS tables of the species of one system, as the pair kernels stage them,
+// for up to MAXSP species (1 in the single-species form).
+template <typename Real, int C, int MAXSP = kMaxSp>
 struct PairTables {
   static constexpr ClassShape S = kClassShapes[C];
   static constexpr int NLJ = S.lj > 0 ? S.lj : 1, NCH = S.ch > 0 ? S.ch : 1;
   static constexpr int NDP = S.dp > 0 ? S.dp : 1, NQD = S.qd > 0 ? S.qd : 1;
-  Real c6[kMaxSp * NLJ][kMaxSp * NLJ];
-  Real c12[kMaxSp * NLJ][kMaxSp * NLJ];
-  int cnt[kMaxSp][4];
-  Real mch[kMaxSp][NCH], mdp[kMaxSp][NDP], mqd[kMaxSp][NQD];   // k_e * magnitude
-  int nsite[kMaxSp][kMaxSp];
+  Real c6[MAXSP * NLJ][MAXSP * NLJ];
+  Real c12[MAXSP * NLJ][MAXSP * NLJ];
+  int cnt[MAXSP][4];
+  Real mch[MAXSP][NCH], mdp[MAXSP][NDP], mqd[MAXSP][NQD];   // k_e * magnitude
+  int nsite[MAXSP][MAXSP];
 
   // nsp: the species in use (1 when every molecule is species 0, whatever
-  // the context holds).  The LJ tables are walked over their full size with
-  // compile-time divisors; entries of unused species are left unset.
+  // the context holds; at most MAXSP).  The LJ tables are walked over their
+  // full size with compile-time divisors; entries of unused species are left
+  // unset.
   __device__ void load(const SpeciesTable* tab, const SysParams& P, int nsp, int tid, int nthreads) {
-    constexpr int W = kMaxSp * NLJ;
+    nsp = min(nsp, MAXSP);
+    constexpr int W = MAXSP * NLJ;
     for (int e = tid; e < W * W; e += nthreads) {
       const int r = e / W, c = e % W;
       const int A = r / NLJ, a = r % NLJ, B = c / NLJ, b = c % NLJ;
@@ -323,7 +326,7 @@ struct ElecParams {
 // cut-off).  Without SITE every site pair of the molecule pair interacts.
 template <typename Real, int C, bool JSIDE, int STRIDE, bool SITE = false, bool ONE = false>
 __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* sj, int spi, int spj,
-                                                   const PairTables<Real, C>& T,
+                                                   const PairTables<Real, C, ONE ? 1 : kMaxSp>& T,
                                                    const ElecParams<Real>& E, Real Rx, Real Ry,
                                                    Real Rz, Real R2, SiteAcc<Real, C>& ai,
                                                    SiteAcc<Real, C>& aj, PairAcc<Real>& acc,
