@@ -230,7 +230,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form of the batched workload")
     ap.add_argument("--no-ewald", action="store_true", help="skip the ionic-solution (Ewald) timing")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-steps", type=int, default=400)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the batched steps directly instead of through a hipGraph")
