@@ -718,17 +718,45 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
   int cnt[kMaxSp];
 #pragma unroll
   for (int s = 0; s < kMaxSp; ++s) cnt[s] = 0;
-  for (int i = tid; i < n; i += 256) {
-    const int s = clamp_species(sd.species[i], P.nsp);
+  // loads of four iterations are issued before their uses (the order of the
+  // additions is unchanged)
+  {
+    int i = tid;
+    for (; i + 3 * 256 < n; i += 4 * 256) {
+      const int s0 = sd.species[i], s1 = sd.species[i + 256], s2 = sd.species[i + 512], s3 = sd.species[i + 768];
+      for (const int sr : {s0, s1, s2, s3}) {
+        const int sp = clamp_species(sr, P.nsp);
 #pragma unroll
-    for (int x = 0; x < kMaxSp; ++x) cnt[x] += (s == x);
+        for (int x = 0; x < kMaxSp; ++x) cnt[x] += (sp == x);
+      }
+    }
+    for (; i < n; i += 256) {
+      const int sp = clamp_species(sd.species[i], P.nsp);
+#pragma unroll
+      for (int x = 0; x < kMaxSp; ++x) cnt[x] += (sp == x);
+    }
   }
   const int ni = sd.nitems;
   const int per = (ni + 255) / 256;
   double acc[kNumBlockSums] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int t = tid * per; t < min(ni, (tid + 1) * per); ++t)
+  {
+    const int t1 = min(ni, (tid + 1) * per);
+    int t = tid * per;
+    for (; t + 4 <= t1; t += 4) {
+      double v[4][kNumBlockSums];
 #pragma unroll
-    for (int k = 0; k < kNumBlockSums; ++k) acc[k] += sd.bsum[(size_t)t * kNumBlockSums + k];
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < kNumBlockSums; ++k) v[u][k] = sd.bsum[(size_t)(t + u) * kNumBlockSums + k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < kNumBlockSums; ++k) acc[k] += v[u][k];
+    }
+    for (; t < t1; ++t)
+#pragma unroll
+      for (int k = 0; k < kNumBlockSums; ++k) acc[k] += sd.bsum[(size_t)t * kNumBlockSums + k];
+  }
 #pragma unroll
   for (int k = 0; k < kNumBlockSums; ++k) s_red[k][tid] = acc[k];
 #pragma unroll
