@@ -225,6 +225,19 @@ __global__ __launch_bounds__(kMdThreads) void md_init_kernel(SlotDev* slots, MDD
 }
 
 // ---------------------------------------------------------------------------
+// Gear predictor on the scaled derivatives y_d = dt^d y^(d) / d! of each
+// component: y_d <- sum over e >= d of C(e, d) y_e (Pascal triangle)
+template <int NC>
+__device__ __forceinline__ void gear_predict(double (&a)[5][NC]) {
+  for (int c = 0; c < NC; ++c) {
+    const double y0 = a[0][c], y1 = a[1][c], y2 = a[2][c], y3 = a[3][c], y4 = a[4][c];
+    a[0][c] = y0 + y1 + y2 + y3 + y4;
+    a[1][c] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
+    a[2][c] = y2 + 3.0 * y3 + 6.0 * y4;
+    a[3][c] = y3 + 4.0 * y4;
+  }
+}
+
 __global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict__ slots, MDDev* md,
                                                        const SysParams* __restrict__ prm,
                                                        const SpeciesTable* __restrict__ tab) {
@@ -236,35 +249,35 @@ __global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict
   if (i >= sd.n) return;
   const int np = sd.com_ld;
   if (m.integrator == MS2_GEAR) {
-    // the Gear arrays are distinct allocations: every load is issued before
-    // the stores (Pascal-triangle predictor on the 5 scaled derivatives of
-    // each of nc components)
-    auto predict = [&](double* __restrict__ y, int nc, double* y0_out) {
-      double a[5][4];
-      for (int d = 0; d < 5; ++d)
-        for (int c = 0; c < nc; ++c) a[d][c] = y[(d * nc + c) * np + i];
-      for (int c = 0; c < nc; ++c) {
-        const double y0 = a[0][c], y1 = a[1][c], y2 = a[2][c], y3 = a[3][c], y4 = a[4][c];
-        y0_out[c] = y0 + y1 + y2 + y3 + y4;
-        y[(1 * nc + c) * np + i] = y1 + 2.0 * y2 + 3.0 * y3 + 4.0 * y4;
-        y[(2 * nc + c) * np + i] = y2 + 3.0 * y3 + 6.0 * y4;
-        y[(3 * nc + c) * np + i] = y3 + 4.0 * y4;
-      }
-    };
-    double* const r = m.r;
-    double* const w = m.w;
-    double* const q = m.q;
+    // every load of the molecule's state is issued before the first store
+    // (the rows of an array lie np apart, which the compiler cannot prove
+    // non-zero); Pascal-triangle predictor on the 5 scaled derivatives of
+    // each component; row 4 is unchanged
     const bool rotating = m.rotating;
-    double p0[4];
-    predict(r, 3, p0);
-    for (int c = 0; c < 3; ++c) r[c * np + i] = p0[c];
+    double* __restrict__ const r = m.r;
+    double* __restrict__ const w = m.w;
+    double* __restrict__ const q = m.q;
+    double R[5][3], W[5][3], Q[5][4];
+    for (int d = 0; d < 5; ++d)
+      for (int c = 0; c < 3; ++c) R[d][c] = r[(d * 3 + c) * np + i];
+    if (rotating)
+      for (int d = 0; d < 5; ++d) {
+        for (int c = 0; c < 3; ++c) W[d][c] = w[(d * 3 + c) * np + i];
+        for (int c = 0; c < 4; ++c) Q[d][c] = q[(d * 4 + c) * np + i];
+      }
+    gear_predict(R);
+    for (int d = 0; d < 4; ++d)
+      for (int c = 0; c < 3; ++c) r[(d * 3 + c) * np + i] = R[d][c];
     if (rotating) {
-      predict(w, 3, p0);
-      for (int c = 0; c < 3; ++c) w[c * np + i] = p0[c];
-      predict(q, 4, p0);
+      gear_predict(W);
+      gear_predict(Q);
       // the force evaluation uses the predicted orientation projected onto |q| = 1
-      const double nq = sqrt(p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2] + p0[3] * p0[3]);
-      for (int c = 0; c < 4; ++c) q[c * np + i] = p0[c] / nq;
+      const double nq = sqrt(Q[0][0] * Q[0][0] + Q[0][1] * Q[0][1] + Q[0][2] * Q[0][2] + Q[0][3] * Q[0][3]);
+      for (int c = 0; c < 4; ++c) Q[0][c] = Q[0][c] / nq;
+      for (int d = 0; d < 4; ++d) {
+        for (int c = 0; c < 3; ++c) w[(d * 3 + c) * np + i] = W[d][c];
+        for (int c = 0; c < 4; ++c) q[(d * 4 + c) * np + i] = Q[d][c];
+      }
     }
   } else {
     const double h = 0.5 * m.dt / tab->sp[clamp_species(sd.species[i], tab->nsp)].mass;
@@ -323,42 +336,56 @@ __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDe
   const double ct[5] = {19.0 / 120.0, 3.0 / 4.0, 1.0, 1.0 / 2.0, 1.0 / 12.0};
   const double cr[5] = {251.0 / 720.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0};
   if (m.integrator == MS2_GEAR) {
-    for (int c = 0; c < 3; ++c) {
-      const double delta = 0.5 * dt * dt * gf[c * ld + i] / D.mass - gr[(2 * 3 + c) * np + i];
-      for (int d = 0; d < 5; ++d) gr[(d * 3 + c) * np + i] += ct[d] * delta;
+    // the whole state of the molecule is loaded before the first store: the
+    // rows of one array lie np apart, a distance the compiler cannot prove
+    // non-zero, so updates in place would chain each load behind the
+    // previous store
+    const bool rotating = m.rotating;
+    const double mass = D.mass, L = P.L, invL = P.invL;
+    double R[5][3], F[3], W[5][3], Q[5][4], T[3];
+    for (int d = 0; d < 5; ++d)
+      for (int c = 0; c < 3; ++c) R[d][c] = gr[(d * 3 + c) * np + i];
+    for (int c = 0; c < 3; ++c) F[c] = gf[c * ld + i];
+    if (rotating) {
+      for (int d = 0; d < 5; ++d) {
+        for (int c = 0; c < 3; ++c) W[d][c] = gw[(d * 3 + c) * np + i];
+        for (int c = 0; c < 4; ++c) Q[d][c] = gq[(d * 4 + c) * np + i];
+      }
+      for (int c = 0; c < 3; ++c) T[c] = gt[c * ld + i];
     }
-    if (m.rotating) {
-      double q[4], w[3], tq[3], tb[3], wd[3], qd[4], A[3][3];
-      for (int c = 0; c < 4; ++c) q[c] = gq[c * np + i];
+    for (int c = 0; c < 3; ++c) {
+      const double delta = 0.5 * dt * dt * F[c] / mass - R[2][c];
+      for (int d = 0; d < 5; ++d) R[d][c] += ct[d] * delta;
+    }
+    if (rotating) {
+      double wd[3], qd[4], tb[3], A[3][3];
+      qrot(Q[0][0], Q[0][1], Q[0][2], Q[0][3], A);
+      body_torque(A, T, tb);
+      euler_rate(D.inertia, tb, W[0], wd);
+      quat_rate(Q[0], W[0], qd);
       for (int c = 0; c < 3; ++c) {
-        w[c] = gw[c * np + i];
-        tq[c] = gt[c * ld + i];
+        const double delta = dt * wd[c] - W[1][c];
+        for (int d = 0; d < 5; ++d) W[d][c] = W[d][c] + cr[d] * delta;
+        wo[c] = W[0][c];
       }
-      qrot(q[0], q[1], q[2], q[3], A);
-      body_torque(A, tq, tb);
-      euler_rate(D.inertia, tb, w, wd);
-      quat_rate(q, w, qd);
-      for (int c = 0; c < 3; ++c) {
-        const double delta = dt * wd[c] - gw[(1 * 3 + c) * np + i];
-        double wv[5];
-        for (int d = 0; d < 5; ++d) wv[d] = gw[(d * 3 + c) * np + i];
-        for (int d = 0; d < 5; ++d) gw[(d * 3 + c) * np + i] = wv[d] + cr[d] * delta;
-        wo[c] = wv[0] + cr[0] * delta;
-      }
-      double q0[4];
       for (int c = 0; c < 4; ++c) {
-        const double delta = dt * qd[c] - gq[(1 * 4 + c) * np + i];
-        for (int d = 0; d < 5; ++d) gq[(d * 4 + c) * np + i] += cr[d] * delta;
-        q0[c] = gq[c * np + i];
+        const double delta = dt * qd[c] - Q[1][c];
+        for (int d = 0; d < 5; ++d) Q[d][c] += cr[d] * delta;
       }
-      const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
-      for (int c = 0; c < 4; ++c) gq[c * np + i] = q0[c] / nq;
+      const double nq = sqrt(Q[0][0] * Q[0][0] + Q[0][1] * Q[0][1] + Q[0][2] * Q[0][2] + Q[0][3] * Q[0][3]);
+      for (int c = 0; c < 4; ++c) Q[0][c] = Q[0][c] / nq;
+      for (int d = 0; d < 5; ++d) {
+        for (int c = 0; c < 3; ++c) gw[(d * 3 + c) * np + i] = W[d][c];
+        for (int c = 0; c < 4; ++c) gq[(d * 4 + c) * np + i] = Q[d][c];
+      }
     }
     for (int c = 0; c < 3; ++c) {
-      gr[c * np + i] = wrap(gr[c * np + i], P.L, P.invL);
-      vo[c] = gr[(1 * 3 + c) * np + i] / dt;
-      gv[c * np + i] = vo[c];
+      R[0][c] = wrap(R[0][c], L, invL);
+      vo[c] = R[1][c] / dt;
     }
+    for (int d = 0; d < 5; ++d)
+      for (int c = 0; c < 3; ++c) gr[(d * 3 + c) * np + i] = R[d][c];
+    for (int c = 0; c < 3; ++c) gv[c * np + i] = vo[c];
   } else {
     const double h = 0.5 * dt / D.mass;
     for (int c = 0; c < 3; ++c) {
@@ -483,17 +510,28 @@ __global__ __launch_bounds__(kMdBlock) void md_rescale_kernel(const SlotDev* __r
   if (i >= sd.n) return;
   const int np = sd.com_ld;
   const double ft = m.scale_tr, fr = m.scale_rot;
-  double* __restrict__ gv = m.vel;
-  double* __restrict__ gr = m.r;
+  const bool gear = m.integrator == MS2_GEAR, rot = m.rotating && fr != 1.0;
+  double* __restrict__ const gv = m.vel;
+  double* __restrict__ const gr = m.r;
+  double* __restrict__ const gw = m.w;
+  double* __restrict__ const gq = m.q;
+  // all loads before the first store (see md_begin_kernel)
+  double v[3], r1[3], w1[3], q1[4];
   for (int c = 0; c < 3; ++c) {
-    gv[c * np + i] *= ft;
-    if (m.integrator == MS2_GEAR) gr[(1 * 3 + c) * np + i] *= ft;
+    v[c] = gv[c * np + i];
+    if (gear) r1[c] = gr[(1 * 3 + c) * np + i];
   }
-  if (m.rotating && fr != 1.0) {
-    double* __restrict__ gw = m.w;
-    double* __restrict__ gq = m.q;
-    for (int c = 0; c < 3; ++c) gw[c * np + i] *= fr;
-    for (int c = 0; c < 4; ++c) gq[(1 * 4 + c) * np + i] *= fr;
+  if (rot) {
+    for (int c = 0; c < 3; ++c) w1[c] = gw[c * np + i];
+    for (int c = 0; c < 4; ++c) q1[c] = gq[(1 * 4 + c) * np + i];
+  }
+  for (int c = 0; c < 3; ++c) {
+    gv[c * np + i] = v[c] * ft;
+    if (gear) gr[(1 * 3 + c) * np + i] = r1[c] * ft;
+  }
+  if (rot) {
+    for (int c = 0; c < 3; ++c) gw[c * np + i] = w1[c] * fr;
+    for (int c = 0; c < 4; ++c) gq[(1 * 4 + c) * np + i] = q1[c] * fr;
   }
 }
 
