@@ -24,6 +24,8 @@ SUM_NAMES = ["u_lj", "u_elec", "u_recip", "u_const", "u_lrc", "virial", "us", "u
              "us_lrc", "uss_lrc", "npair", "nsite"]
 NSUM = len(SUM_NAMES)
 MOMENT_NAMES = ["n", "x", "xx", "xxx", "y", "xy", "xxy", "yy", "xyy", "z", "xz"]
+# columns of the per-step energy log of md(): U, K_trans, K_rot, W, U_s + U_s,lrc, U_ss + U_ss,lrc
+LOG_COLS = 6
 
 c_double, c_int32 = ctypes.c_double, ctypes.c_int32
 
@@ -182,7 +184,7 @@ def md(system, md_settings=None, want_log: bool = True):
     vel = np.ascontiguousarray(st.vel, dtype=np.float64).copy()
     omega = np.ascontiguousarray(st.omega, dtype=np.float64).copy()
     com, quat = com.copy(), quat.copy()
-    log = np.zeros((m.n_steps + 1, 4)) if want_log else None
+    log = np.zeros((m.n_steps + 1, LOG_COLS)) if want_log else None
     moments = np.zeros(len(MOMENT_NAMES))
     T = rdf_ntypes(st.species)
     rdf = np.zeros((T * (T + 1) // 2, max(m.rdf_bins, 1)))

@@ -900,6 +900,18 @@ static void moment_sample(const double* sums, double V, double u0, double* m) {
   m[OR_M_XZ] += X * Z;
 }
 
+/* One row of the energy log: U, K_trans, K_rot, W, and the two volume
+ * derivatives in s (explicit + tail), from which dU/dV and d2U/dV2 follow
+ * (Sec. 3). */
+static void log_row(double* row, const double* sums, double ktr, double krot) {
+  row[0] = u_total(sums);
+  row[1] = ktr;
+  row[2] = krot;
+  row[3] = sums[OR_VIRIAL];
+  row[4] = sums[OR_US] + sums[OR_US_LRC];
+  row[5] = sums[OR_USS] + sums[OR_USS_LRC];
+}
+
 static void wrap_box(double* x, int n3, double L) {
   for (int c = 0; c < n3; ++c) x[c] -= L * floor(x[c] / L);
 }
@@ -996,8 +1008,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
     double ktr = 0.0;
     for (int i = 0; i < n; ++i) ktr += 0.5 * sp[species[i]].mass * dot3(vel + 3 * i, vel + 3 * i);
     if (energy_log) {
-      energy_log[0] = u_total(sums); energy_log[1] = ktr; energy_log[2] = 0.0;
-      energy_log[3] = sums[OR_VIRIAL];
+      log_row(energy_log, sums, ktr, 0.0);
     }
     if (acf.n) acf_sample(&acf, 0, vel, sp, species, acf_v, acf_j, acf_cnt);
     if (res.on) residence_sample(&res, 0, com, L, res_acf, res_cnt, solvation);
@@ -1030,8 +1041,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
         for (int i = 0; i < n; ++i) k2 += sp[species[i]].mass * dot3(vel + 3 * i, vel + 3 * i);
       }
       if (energy_log) {
-        energy_log[4 * s + 0] = u_total(sums); energy_log[4 * s + 1] = 0.5 * k2;
-        energy_log[4 * s + 2] = 0.0; energy_log[4 * s + 3] = sums[OR_VIRIAL];
+        log_row(energy_log + OR_LOG_COLS * s, sums, 0.5 * k2, 0.0);
       }
       if (moments && cfg->sample_every > 0 && s % cfg->sample_every == 0)
         moment_sample(sums, V, cfg->u0, moments);
@@ -1080,8 +1090,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
         ktr += 0.5 * s->mass * dot3(vel + 3 * i, vel + 3 * i);
         for (int k = 0; k < 3; ++k) krot += 0.5 * s->inertia[k] * omega[3 * i + k] * omega[3 * i + k];
       }
-      energy_log[0] = u_total(sums); energy_log[1] = ktr; energy_log[2] = krot;
-      energy_log[3] = sums[OR_VIRIAL];
+      log_row(energy_log, sums, ktr, krot);
     }
     if (acf.n) acf_sample(&acf, 0, vel, sp, species, acf_v, acf_j, acf_cnt);
     if (res.on) residence_sample(&res, 0, com, L, res_acf, res_cnt, solvation);
@@ -1154,8 +1163,7 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
         }
       }
       if (energy_log) {
-        energy_log[4 * s + 0] = u_total(sums); energy_log[4 * s + 1] = 0.5 * k2;
-        energy_log[4 * s + 2] = 0.5 * kr2; energy_log[4 * s + 3] = sums[OR_VIRIAL];
+        log_row(energy_log + OR_LOG_COLS * s, sums, 0.5 * k2, 0.5 * kr2);
       }
       if (moments && cfg->sample_every > 0 && s % cfg->sample_every == 0)
         moment_sample(sums, V, cfg->u0, moments);

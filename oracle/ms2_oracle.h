@@ -113,6 +113,9 @@ enum {
   OR_M_YY, OR_M_XYY, OR_M_Z, OR_M_XZ, OR_NMOM
 };
 
+/* columns of one row of or_md's energy log */
+#define OR_LOG_COLS 6
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -130,8 +133,9 @@ int or_kspace(const or_species* sp, int32_t nsp, const or_params* p,
               double* sums);
 
 /* Runs cfg->n_steps steps in place on com/quat/vel/omega (vel lab frame,
- * omega body frame).  energy_log[(n_steps+1)*4] receives, per step and for
- * the initial state, (U_total, K_trans, K_rot, W).  moments[OR_NMOM];
+ * omega body frame).  energy_log[(n_steps+1)*OR_LOG_COLS] receives, per step
+ * and for the initial state, (U_total, K_trans, K_rot, W, U_s + U_s,lrc,
+ * U_ss + U_ss,lrc).  moments[OR_NMOM];
  * rdf[npairtypes*rdf_bins] (counts as doubles, unordered site pairs);
  * acf_v[acf_nlag], acf_j[acf_nlag], acf_cnt[acf_nlag]: raw sums over
  * origins of (1/N) sum_i v_i(t0).v_i(t0+l n), of j_e(t0).j_e(t0+l n), and

@@ -176,9 +176,15 @@ def test_lustig_moments_match_the_per_step_sums():
     steps = [2, 4, 6]
     X = log[steps, 0] - s.md.u0
     Y = (-log[steps, 3] + us_lrc) / (3 * V)
+    # the logged dU/ds is the same quantity as -W plus the tail
+    np.testing.assert_allclose(log[steps, 4], -log[steps, 3] + us_lrc, rtol=1e-12)
+    # Z = d2U/dV2 of each sampled step from its logged s-derivatives; the value
+    # of this conversion is pinned against scaled energies in
+    # test_oracle_volume_moment_pins.py
+    Z = (log[steps, 5] - 2 * log[steps, 4]) / (9 * V * V)
     ref = [3, X.sum(), (X * X).sum(), (X ** 3).sum(), Y.sum(), (X * Y).sum(), (X * X * Y).sum(),
-           (Y * Y).sum(), (X * Y * Y).sum()]
-    np.testing.assert_allclose(m[:9], ref, rtol=1e-10)
+           (Y * Y).sum(), (X * Y * Y).sum(), Z.sum(), (X * Z).sum()]
+    np.testing.assert_allclose(m, ref, rtol=1e-10)
     # virial route: dU/dV = -(W/(3V) + p_lrc)
     y0 = (su[US] + su[US_LRC]) / (3 * V)
     assert y0 == pytest.approx(-(su[VIR] / (3 * V) - su[US_LRC] / (3 * V)), rel=1e-12)
