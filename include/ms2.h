@@ -139,7 +139,11 @@ void ms2_destroy(ms2_ctx* ctx);
  * d_quat double[4][n].  Scratch is owned by the context and grows on the
  * first call at a larger n_mol (that call allocates; later ones do not).
  * Errors: MS2_EINVAL (n_mol < 2, rc >= L/2, Ewald with multipoles, NULL
- * pointers, ...), MS2_ENOMEM, MS2_EDEVICE. */
+ * pointers, ...), MS2_ENOMEM, MS2_EDEVICE.  A species index outside
+ * [0, n_species) in d_species is found on the device, where the call cannot
+ * return it: that molecule's force and torque and every energy, virial and
+ * volume-derivative sum of the call become NaN, and ms2_device_errors
+ * reports MS2_EINVAL. */
 ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
                       const int32_t* d_species, const double* d_com, const double* d_quat,
                       double* d_force, double* d_torque, double* d_sums, void* stream);
@@ -149,11 +153,22 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
  * accumulated in FP64; tin-foil boundary.  ACCUMULATES (+=) reciprocal
  * forces and torques into d_force/d_torque and U_RECIP, VIRIAL (molecular)
  * and US into d_sums, so call it after ms2_forces on the same stream.
- * Errors: MS2_EINVAL if elec != MS2_ELEC_EWALD or arguments are bad. */
+ * Errors: MS2_EINVAL if elec != MS2_ELEC_EWALD or arguments are bad.  A
+ * species index outside [0, n_species) makes S(k), and with it every
+ * reciprocal force, torque and sum of the call, NaN, and is reported by
+ * ms2_device_errors. */
 ms2_status ms2_ewald_kspace(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
                             const int32_t* d_species, const double* d_com,
                             const double* d_quat, double* d_force, double* d_torque,
                             double* d_sums, void* stream);
+
+/* Argument errors that only the device can see (a species index outside
+ * the table in the arrays of ms2_forces / ms2_ewald_kspace).  Synchronizes
+ * `stream`, then returns MS2_EINVAL if any call on this context recorded
+ * such an error since the last ms2_device_errors, and clears the record;
+ * MS2_OK otherwise.  Batch slots validate their species at admission and
+ * never record one. */
+ms2_status ms2_device_errors(ms2_ctx* ctx, void* stream);
 
 /* ----------------------------------------------------------------------- */
 /* Batched, device-resident simulation (many independent systems)          */
@@ -234,10 +249,18 @@ enum {
 
 /* Advances every active slot by up to n_steps MD steps on the device: per
  * step a predictor (Gear) or drift (VV), the force path of ms2_forces and
- * ms2_ewald_kspace for all slots at once, the corrector, the isokinetic
- * thermostat and the samplers (Lustig moments, RDF, ACFs on the extended
- * time step).  A slot whose own step budget runs out stops advancing.
- * Asynchronous; nothing is copied to the host. */
+ * ms2_ewald_kspace for all slots at once (Sec. 2: the partner search, energy
+ * and force loops over molecules that dominate each step), the corrector,
+ * the isokinetic thermostat and the samplers: Lustig moments every
+ * sample_every steps (Sec. 3, Eq. 1), the RDF (Sec. 5, Eq. 2) and the
+ * autocorrelation functions on the extended time step of acf_every MD steps
+ * (Sec. 4, transport properties).  Integrators: velocity Verlet for point
+ * molecules; for rigid molecules a 5-value Gear predictor-corrector of the
+ * centres and of the quaternions with the body-frame Euler equations (the
+ * paper leaves the integrator to its predecessor release; this is the
+ * textbook scheme).  A slot whose own step budget runs out stops advancing.
+ * Asynchronous; nothing is copied to the host.  Errors: MS2_EINVAL (NULL
+ * batch, n_steps < 0), MS2_EDEVICE. */
 ms2_status ms2_step(ms2_batch* batch, int32_t n_steps, int32_t flags, void* stream);
 
 /* Elapsed time of the pair-kernel launches of the last ms2_step call made

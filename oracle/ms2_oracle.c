@@ -934,6 +934,9 @@ int or_md(const or_species* sp, int32_t nsp, const or_params* p, const or_md_cfg
     for (int k = 0; k < 3; ++k)
       if (sp[s].inertia[k] > 0.0) rotating = 1;
   if (cfg->integrator == OR_VV && rotating) return -33;
+  /* Massieu moments need d2U/dV2, which the reciprocal sum does not supply;
+   * the paper does not combine them with Ewald summation (Sec. 4) */
+  if (cfg->sample_every > 0 && p->elec == OR_ELEC_EWALD) return -36;
 
   double L = p->box, V = L * L * L, dt = cfg->dt;
   size_t n3 = 3 * (size_t)n, n4 = 4 * (size_t)n;

@@ -473,6 +473,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   d.kvec = kv;
   d.nk = nk;
   d.mtiles = mtiles;
+  d.err = ctx->d_err;
   MS2_HIP(hipMemcpyAsync(r->d_slot, r->h_slot, sizeof(SlotDev), hipMemcpyHostToDevice, st));
   MS2_HIP(hipMemcpyAsync(r->d_prm, r->h_prm, sizeof(SysParams), hipMemcpyHostToDevice, st));
   *ring_out = r;
@@ -513,6 +514,8 @@ ms2_status ms2_create(ms2_ctx** out, const ms2_species* h_species, int32_t n_spe
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipMalloc(&c->d_tab, sizeof(SpeciesTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, &c->tab, sizeof(SpeciesTable), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(int));
   for (int k = 0; k < kRing && e == hipSuccess; ++k) {
     RingSlot& r = c->ring[k];
     e = hipHostMalloc((void**)&r.h_slot, sizeof(SlotDev), hipHostMallocDefault);
@@ -543,6 +546,7 @@ void ms2_destroy(ms2_ctx* c) {
     if (r.ev) (void)hipEventDestroy(r.ev);
   }
   if (c->d_tab) (void)hipFree(c->d_tab);
+  if (c->d_err) (void)hipFree(c->d_err);
   c->s_sites.release();
   c->s_pf.release();
   c->s_bsum.release();
@@ -593,6 +597,19 @@ ms2_status ms2_ewald_kspace(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_
                         d.kchunks, st));
   MS2_HIP(hipEventRecord(r->ev, st));
   return MS2_OK;
+}
+
+ms2_status ms2_device_errors(ms2_ctx* ctx, void* stream) {
+  if (!ctx) return set_error(MS2_EINVAL, "context is NULL");
+  MS2_HIP(hipSetDevice(ctx->device));
+  MS2_HIP(hipStreamSynchronize((hipStream_t)stream));
+  int word = 0;
+  MS2_HIP(hipMemcpy(&word, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (!word) return MS2_OK;
+  const int zero = 0;
+  MS2_HIP(hipMemcpy(ctx->d_err, &zero, sizeof(int), hipMemcpyHostToDevice));
+  return set_error(MS2_EINVAL, "a device species array held an index outside [0, n_species): "
+                               "the outputs of that call are NaN");
 }
 
 ms2_status ms2_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_t precision,

@@ -161,6 +161,9 @@ struct ms2_batch {
   int max_slots = 0;
   size_t budget = 0, used_bytes = 0;
   std::vector<SlotHost> slots;
+  // allocations of retired slots, kept for later admissions: hipFree waits
+  // for the whole device, which would stall other batches' work in flight
+  std::vector<DevBuf> pool;
   DevBuf d_slots, d_md, d_prm, d_items;
   // work items grouped by (precision, waves): [begin, end) into d_items
   struct Group { int precision, waves, begin, end; bool heat_flux, site_cut; };
@@ -259,6 +262,12 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
     s.acf_nlag = sys->acf_nlag;
     s.acf_max_live = (int)((long long)sys->acf_nlag * sys->acf_every / sys->acf_origin_every + 2);
   }
+  if (sys->sample_every > 0 && sys->params.elec == MS2_ELEC_EWALD)
+    // the reciprocal part has no d2U/ds2 here, so Z = d2U/dV2 and the
+    // derivatives built on it would be wrong; the paper does not combine
+    // Massieu sampling with Ewald summation either (Sec. 4)
+    return set_error(MS2_EINVAL, "Lustig moment sampling (sample_every > 0) is not offered with Ewald summation");
+  if (sys->sample_every < 0) return set_error(MS2_EINVAL, "sample_every must be >= 0");
   if (sys->heat_flux) {
     if (sys->acf_every <= 0) return set_error(MS2_EINVAL, "the heat flux is sampled with the ACFs: acf_every > 0");
     if (sys->params.elec == MS2_ELEC_EWALD)
@@ -329,7 +338,10 @@ void rebuild_items(ms2_batch* b) {
     }
   }
   if (!all.empty()) {
-    (void)b->d_items.ensure(all.size() * sizeof(WorkItem));
+    // grown with headroom: a reallocation waits for the whole device
+    size_t need = all.size() * sizeof(WorkItem);
+    if (need > b->d_items.bytes) need += need / 2;
+    (void)b->d_items.ensure(need);
     (void)hipMemcpy(b->d_items.p, all.data(), all.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
   }
   b->dirty = false;
@@ -424,6 +436,7 @@ void ms2_batch_destroy(ms2_batch* b) {
   for (auto e : b->ev_begin) (void)hipEventDestroy(e);
   for (auto e : b->ev_end) (void)hipEventDestroy(e);
   for (auto& s : b->slots) s.mem.release();
+  for (auto& m : b->pool) m.release();
   b->d_slots.release();
   b->d_md.release();
   b->d_prm.release();
@@ -460,6 +473,16 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
     return set_error(MS2_ENOMEM, "HBM budget of the batch exceeded");
   MS2_HIP(hipSetDevice(ctx->device));
   SlotHost& h = b->slots[slot];
+  {
+    // the smallest pooled allocation that holds the slot, else a new one
+    int best = -1;
+    for (int k = 0; k < (int)b->pool.size(); ++k)
+      if (b->pool[k].bytes >= lay.total && (best < 0 || b->pool[k].bytes < b->pool[best].bytes)) best = k;
+    if (best >= 0) {
+      h.mem = b->pool[best];
+      b->pool.erase(b->pool.begin() + best);
+    }
+  }
   MS2_HIP(h.mem.ensure(lay.total));
   MS2_HIP(hipMemsetAsync(h.mem.p, 0, lay.total, st));
   char* base = (char*)h.mem.p;
@@ -652,7 +675,16 @@ ms2_status ms2_slot_retire(ms2_batch* b, int32_t slot) {
   MS2_HIP(hipMemcpy((SlotDev*)b->d_slots.p + slot, &z, sizeof(SlotDev), hipMemcpyHostToDevice));
   MS2_HIP(hipMemcpy((MDDev*)b->d_md.p + slot, &zm, sizeof(MDDev), hipMemcpyHostToDevice));
   b->used_bytes -= h.lay.total;
-  h.mem.release();
+  // keep the allocation for a later admission; beyond one per slot of the
+  // batch the smallest pooled one is freed
+  b->pool.push_back(h.mem);
+  h.mem = DevBuf{};
+  if ((int)b->pool.size() > b->max_slots) {
+    auto it = std::min_element(b->pool.begin(), b->pool.end(),
+                               [](const DevBuf& x, const DevBuf& y) { return x.bytes < y.bytes; });
+    it->release();
+    b->pool.erase(it);
+  }
   h.used = false;
   b->dirty = true;
   drop_graph(b);

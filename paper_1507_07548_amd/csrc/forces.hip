@@ -24,6 +24,7 @@
 
 #include "internal.h"
 #include "pair_math.h"
+#include "quat.h"
 
 namespace ms2 {
 
@@ -32,18 +33,6 @@ namespace ms2 {
 // Record layout per class: [lj 3*NLJ][ch 3*NCH][dp 6*NDP][qd 6*NQD], each
 // real stored as a row of length npad (structure of arrays).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void rot_matrix(double w, double x, double y, double z, double A[3][3]) {
-  A[0][0] = 1.0 - 2.0 * (y * y + z * z);
-  A[0][1] = 2.0 * (x * y - w * z);
-  A[0][2] = 2.0 * (x * z + w * y);
-  A[1][0] = 2.0 * (x * y + w * z);
-  A[1][1] = 1.0 - 2.0 * (x * x + z * z);
-  A[1][2] = 2.0 * (y * z - w * x);
-  A[2][0] = 2.0 * (x * z - w * y);
-  A[2][1] = 2.0 * (y * z + w * x);
-  A[2][2] = 1.0 - 2.0 * (x * x + y * y);
-}
-
 template <typename Real, int C>
 __global__ __launch_bounds__(256) void site_frame_kernel(const SlotDev* __restrict__ slots,
                                                          const SysParams* __restrict__ prm,
@@ -58,7 +47,7 @@ __global__ __launch_bounds__(256) void site_frame_kernel(const SlotDev* __restri
   Real* out = reinterpret_cast<Real*>(sd.sites);
   const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
   double A[3][3];
-  rot_matrix(sd.quat[i], sd.quat[ld + i], sd.quat[2 * ld + i], sd.quat[3 * ld + i], A);
+  quat_matrix(sd.quat[i], sd.quat[ld + i], sd.quat[2 * ld + i], sd.quat[3 * ld + i], A);
   int k = 0;
   auto put = [&](const double* b, int valid) {
     for (int c = 0; c < 3; ++c) {
@@ -671,7 +660,8 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
 //    contiguous run, then a tree), species counts, Ewald constants and the LJ
 //    tail.  OVERWRITES sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __restrict__ slots) {
+__global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __restrict__ slots,
+                                                           const SysParams* __restrict__ prm) {
   // one thread per (component, molecule): the grid's x holds six runs of
   // molecule blocks, one per force/torque component, so that the largest
   // systems' serial chains are one component long
@@ -682,7 +672,8 @@ __global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __rest
   if (i >= sd.n) return;
   const int np = sd.npad, ld = sd.com_ld, nparts = sd.jsplits;
   const size_t stride = (size_t)6 * np;
-  double v = 0.0;
+  // a species index outside the table makes this molecule's result NaN
+  double v = species_ok(sd.species[i], prm[blockIdx.y].nsp) ? 0.0 : __builtin_nan("");
   // the loads of four partials are issued before their additions, which
   // keep the order p = 0, 1, 2, ...
   auto reduce = [&](auto* __restrict__ pf) {
@@ -718,6 +709,7 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
   int cnt[kMaxSp];
 #pragma unroll
   for (int s = 0; s < kMaxSp; ++s) cnt[s] = 0;
+  int bad = 0;                               // species indices outside the table
   // loads of four iterations are issued before their uses (the order of the
   // additions is unchanged)
   {
@@ -725,12 +717,14 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
     for (; i + 3 * 256 < n; i += 4 * 256) {
       const int s0 = sd.species[i], s1 = sd.species[i + 256], s2 = sd.species[i + 512], s3 = sd.species[i + 768];
       for (const int sr : {s0, s1, s2, s3}) {
+        bad += species_ok(sr, P.nsp) ? 0 : 1;
         const int sp = clamp_species(sr, P.nsp);
 #pragma unroll
         for (int x = 0; x < kMaxSp; ++x) cnt[x] += (sp == x);
       }
     }
     for (; i < n; i += 256) {
+      bad += species_ok(sd.species[i], P.nsp) ? 0 : 1;
       const int sp = clamp_species(sd.species[i], P.nsp);
 #pragma unroll
       for (int x = 0; x < kMaxSp; ++x) cnt[x] += (sp == x);
@@ -761,7 +755,7 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
   for (int k = 0; k < kNumBlockSums; ++k) s_red[k][tid] = acc[k];
 #pragma unroll
   for (int x = 0; x < kMaxSp; ++x) s_cnt[x][tid] = cnt[x];
-  __syncthreads();
+  const bool any_bad = __syncthreads_or(bad);
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) {
       for (int k = 0; k < kNumBlockSums; ++k) s_red[k][tid] += s_red[k][tid + h];
@@ -799,6 +793,11 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
     out[MS2_SUM_U_LRC] = ul;
     out[MS2_SUM_US_LRC] = usl;
     out[MS2_SUM_USS_LRC] = ussl;
+    if (any_bad) {
+      // an argument error found on the device: no sum of this call is valid
+      for (int k = 0; k < MS2_SUM_NPAIR; ++k) out[k] = __builtin_nan("");
+      if (sd.err) *sd.err = 1;
+    }
   }
 }
 
@@ -898,7 +897,7 @@ hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool s
 
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_force_kernel, dim3(6 * ((max_n + 255) / 256), nslots), dim3(256), 0, st, slots);
+  hipLaunchKernelGGL(reduce_force_kernel, dim3(6 * ((max_n + 255) / 256), nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(reduce_sums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
   return hipGetLastError();
 }

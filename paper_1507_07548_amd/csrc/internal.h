@@ -114,13 +114,17 @@ struct SlotDev {
   double* ksum;               // [4]: U_recip, W_atomic, sum d.F, spare
   const struct KVec* kvec;    // [nk] half-space integer vectors
   int nk, mtiles;             // k vectors; kMolTile-molecule tiles of the reciprocal-force kernel
+  int* err;                   // device error word (1: a species index outside the table), or NULL
 };
 
-// Species indices come from caller memory: clamp them into the table so a
-// bad index can never address outside it.
+// Species indices come from caller memory.  Every load clamps them into the
+// table so a bad index can never address outside it; the kernels that end
+// a call (the force and sum reductions, the structure factor) also test them
+// and turn a bad index into NaN outputs and the slot's error word.
 __host__ __device__ inline int clamp_species(int s, int nsp) {
   return s < 0 ? 0 : (s >= nsp ? nsp - 1 : s);
 }
+__host__ __device__ inline bool species_ok(int s, int nsp) { return (unsigned)s < (unsigned)nsp; }
 
 // A pair-kernel work item: molecules [i0, i0 + 64 W) of a slot against
 // j in [j0, j1); `part` selects the per-molecule partial buffer of the i

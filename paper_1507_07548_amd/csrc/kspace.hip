@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "quat.h"
 
 namespace ms2 {
 
@@ -27,16 +28,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.14159265358979323846264338328;
 
 __device__ __forceinline__ void quat_rot(const double* q, int ld, int i, double A[3][3]) {
-  const double w = q[i], x = q[ld + i], y = q[2 * ld + i], z = q[3 * ld + i];
-  A[0][0] = 1.0 - 2.0 * (y * y + z * z);
-  A[0][1] = 2.0 * (x * y - w * z);
-  A[0][2] = 2.0 * (x * z + w * y);
-  A[1][0] = 2.0 * (x * y + w * z);
-  A[1][1] = 1.0 - 2.0 * (x * x + z * z);
-  A[1][2] = 2.0 * (y * z - w * x);
-  A[2][0] = 2.0 * (x * z - w * y);
-  A[2][1] = 2.0 * (y * z + w * x);
-  A[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  quat_matrix(q[i], q[ld + i], q[2 * ld + i], q[3 * ld + i], A);
 }
 
 // exp(i 2 pi t) with t reduced by its nearest integer first
@@ -93,7 +85,8 @@ __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slot
   const int i = mc * kMolTile + (lane >> 2), a = lane & (kChargeSlots - 1);
   double q = 0.0, x = 0.0, y = 0.0, z = 0.0;
   if (i < sd.n) {
-    const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], P.nsp)];
+    const int spr = sd.species[i];
+    const SpeciesDev& D = tab->sp[clamp_species(spr, P.nsp)];
     if (a < min(D.nch, kChargeSlots)) {
       double A[3][3];
       quat_rot(sd.quat, ld, i, A);
@@ -102,6 +95,12 @@ __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slot
       y = sd.com[ld + i] + A[1][0] * b[0] + A[1][1] * b[1] + A[1][2] * b[2];
       z = sd.com[2 * ld + i] + A[2][0] * b[0] + A[2][1] * b[1] + A[2][2] * b[2];
       q = D.ch_q[a];
+    }
+    if (!species_ok(spr, P.nsp)) {
+      // an argument error found on the device: S(k), and with it every
+      // reciprocal result of the call, becomes NaN
+      q = __builtin_nan("");
+      if (a == 0 && sd.err) *sd.err = 1;
     }
   }
   __syncthreads();

@@ -25,20 +25,9 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "quat.h"
 
 namespace ms2 {
-
-__device__ __forceinline__ void qrot(double w, double x, double y, double z, double A[3][3]) {
-  A[0][0] = 1.0 - 2.0 * (y * y + z * z);
-  A[0][1] = 2.0 * (x * y - w * z);
-  A[0][2] = 2.0 * (x * z + w * y);
-  A[1][0] = 2.0 * (x * y + w * z);
-  A[1][1] = 1.0 - 2.0 * (x * x + z * z);
-  A[1][2] = 2.0 * (y * z - w * x);
-  A[2][0] = 2.0 * (x * z - w * y);
-  A[2][1] = 2.0 * (y * z + w * x);
-  A[2][2] = 1.0 - 2.0 * (x * x + y * y);
-}
 
 // d/dt of the quaternion for a body-frame angular velocity: (1/2) q (x) (0, w)
 __device__ __forceinline__ void quat_rate(const double* q, const double* w, double* out) {
@@ -188,7 +177,7 @@ __global__ __launch_bounds__(kMdThreads) void md_init_kernel(SlotDev* slots, MDD
           w[c] = m.w[c * np + i];
           tq[c] = sd.torque[c * sd.com_ld + i];
         }
-        qrot(q[0], q[1], q[2], q[3], A);
+        quat_matrix(q[0], q[1], q[2], q[3], A);
         body_torque(A, tq, tb);
         euler_rate(D.inertia, tb, w, wd);
         quat_rate(q, w, qd);
@@ -359,7 +348,7 @@ __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDe
     }
     if (rotating) {
       double wd[3], qd[4], tb[3], A[3][3];
-      qrot(Q[0][0], Q[0][1], Q[0][2], Q[0][3], A);
+      quat_matrix(Q[0][0], Q[0][1], Q[0][2], Q[0][3], A);
       body_torque(A, T, tb);
       euler_rate(D.inertia, tb, W[0], wd);
       quat_rate(Q[0], W[0], qd);
@@ -593,7 +582,7 @@ __global__ __launch_bounds__(64 * W) void rdf_kernel(const WorkItem* __restrict_
   const int spi = clamp_species(sd.species[ic], nsp);
   const SpeciesDev& Di = tab->sp[spi];
   double A[3][3];
-  qrot(sd.quat[ic], sd.quat[ld + ic], sd.quat[2 * ld + ic], sd.quat[3 * ld + ic], A);
+  quat_matrix(sd.quat[ic], sd.quat[ld + ic], sd.quat[2 * ld + ic], sd.quat[3 * ld + ic], A);
   double di[kRdfLj][3];
 #pragma unroll
   for (int a = 0; a < kRdfLj; ++a)
@@ -613,7 +602,7 @@ __global__ __launch_bounds__(64 * W) void rdf_kernel(const WorkItem* __restrict_
       const int spj = clamp_species(sd.species[jc], nsp);
       const SpeciesDev& Dj = tab->sp[spj];
       double B[3][3];
-      qrot(sd.quat[jc], sd.quat[ld + jc], sd.quat[2 * ld + jc], sd.quat[3 * ld + jc], B);
+      quat_matrix(sd.quat[jc], sd.quat[ld + jc], sd.quat[2 * ld + jc], sd.quat[3 * ld + jc], B);
       s_com[0][tid] = sd.com[jc];
       s_com[1][tid] = sd.com[ld + jc];
       s_com[2][tid] = sd.com[2 * ld + jc];

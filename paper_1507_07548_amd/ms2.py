@@ -84,7 +84,7 @@ EXPORTED = ["ms2_create", "ms2_destroy", "ms2_forces", "ms2_ewald_kspace", "ms2_
             "ms2_batch_destroy", "ms2_slot_footprint", "ms2_slot_admit", "ms2_slot_retire",
             "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_set_tile_config",
             "ms2_autotune", "ms2_batch_timing", "ms2_massieu", "ms2_massieu_properties",
-            "ms2_last_error"]
+            "ms2_device_errors", "ms2_last_error"]
 
 
 def lib():
@@ -100,6 +100,7 @@ def lib():
         L.ms2_destroy.restype = None
         for fn in (L.ms2_forces, L.ms2_ewald_kspace):
             fn.argtypes = [vp, P(Params), c_int32, vp, vp, vp, vp, vp, vp, vp]
+        L.ms2_device_errors.argtypes = [vp, vp]
         L.ms2_batch_create.argtypes = [vp, c_int32, c_size_t, c_int32, P(vp)]
         L.ms2_batch_timing.argtypes = [vp, P(c_double), P(c_int32)]
         L.ms2_batch_destroy.argtypes = [vp]
@@ -194,6 +195,11 @@ class Context:
         check(lib().ms2_ewald_kspace(self.handle, ctypes.byref(params), n, species.data_ptr(),
                                      com.data_ptr(), quat.data_ptr(), force.data_ptr(), torque.data_ptr(),
                                      sums.data_ptr(), _stream_ptr(stream)))
+
+    def device_errors(self, stream=None):
+        """ms2_device_errors: raises MS2Error if a call recorded a species
+        index outside the table since the last check (and clears it)."""
+        check(lib().ms2_device_errors(self.handle, _stream_ptr(stream)))
 
     def tile_config(self, n: int, precision: int, mode: int = 1):
         w, j = c_int32(), c_int32()

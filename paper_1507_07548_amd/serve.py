@@ -2,23 +2,29 @@
 
 Requests (a model family, a system and its MD/sampling settings) arrive over
 time.  Each model family owns a backend (a context + batch on its own HIP
-stream).  The loop alternates
-  1. admission: arrived requests, in arrival order, are admitted while a slot
-     is free in their family's batch and the total device footprint of all
-     admitted systems stays within the HBM budget (the first request that
-     does not fit blocks the ones behind it);
-  2. a chunk of `chunk_steps` MD steps for every family with work, launched
-     on the families' streams so that their kernels overlap on the device;
-  3. completion: slots that reached their step budget (or failed) are
-     sampled, retired, and their memory returned to the budget.
+stream), and every family progresses on its own: the loop repeatedly
+  1. completion: for each family whose last chunk of MD steps has finished
+     on the device, slots that reached their step budget (or failed) are
+     sampled, retired, and their memory returned to the budget;
+  2. admission: arrived requests, in arrival order, are admitted into their
+     family's batch while it is idle (no chunk in flight), a slot is free
+     and the total device footprint of all admitted systems stays within the
+     HBM budget.  The first request that does not fit the budget blocks the
+     ones behind it; a family that is busy or full holds back its own later
+     requests only.  A request that can never run -- larger than the whole
+     budget, or refused by its backend while nothing at all is running -- is
+     returned at once as a failed result with the backend's status;
+  3. launch: every idle family with active slots starts its next chunk of
+     `chunk_steps` steps on its stream, so that the families' kernels
+     overlap on the device and a new arrival waits at most for its own
+     family's chunk.
 Latency of a request = completion time - arrival time (wall clock).
 
-Backends expose footprint / admit / step / sync / poll / collect / retire /
-active, so the scheduler runs unchanged against a fake backend on the CPU.
+Backends expose footprint / admit / active / launch / ready / poll / collect
+/ retire, so the scheduler runs unchanged against a fake backend on the CPU.
 """
 from __future__ import annotations
 
-import collections
 import dataclasses
 import time
 from typing import Any, Callable, Dict, List, Optional
@@ -63,7 +69,9 @@ class GpuBackend:
             self.ctx.autotune(*autotune)
         self.batch = ms2.Batch(self.ctx, max_slots)
         self.stream = stream or torch.cuda.Stream()
+        self.event = torch.cuda.Event()
         self.slots: Dict[int, int] = {}       # slot -> requested steps
+        self.last_status = 0
 
     def footprint(self, system, precision) -> int:
         return self.batch.footprint(system, precision)
@@ -73,6 +81,7 @@ class GpuBackend:
             slot = self.batch.admit(system, precision, stream=self.stream)
         except self.ms2.MS2Error as e:
             if e.status in (2, 5):            # no memory / no slot: try later
+                self.last_status = e.status
                 return None
             raise
         self.slots[slot] = system.md.n_steps
@@ -81,11 +90,14 @@ class GpuBackend:
     def active(self) -> int:
         return len(self.slots)
 
-    def step(self, k: int):
+    def launch(self, k: int):
+        """Enqueue k steps of every active slot (asynchronous)."""
         self.batch.step(k, graph=True, stream=self.stream)
+        self.event.record(self.stream)
 
-    def sync(self):
-        self.stream.synchronize()
+    def ready(self) -> bool:
+        """True once the last launched chunk has finished on the device."""
+        return self.event.query()
 
     def poll(self):
         out = []
@@ -105,49 +117,38 @@ class GpuBackend:
 class Server:
     def __init__(self, backends: Dict[str, Any], hbm_budget: int, chunk_steps: int = 100,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, keep_samples: bool = True):
+                 sleep: Callable[[float], None] = time.sleep, keep_samples: bool = True,
+                 poll_s: float = 2e-4):
         self.backends = backends
         self.budget = hbm_budget
         self.chunk = chunk_steps
         self.clock = clock
         self.sleep = sleep
         self.keep_samples = keep_samples
+        self.poll_s = poll_s
         self.log: List[tuple] = []            # (time, event, rid)
 
     def run(self, requests: List[Request]) -> List[Result]:
-        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        pending: List[Request] = sorted(requests, key=lambda r: (r.arrival, r.rid))
         running: Dict[tuple, tuple] = {}     # (model, slot) -> (request, footprint, admitted)
+        inflight = set()                      # families with a chunk on the device
         used = 0
         results: List[Result] = []
         t0 = self.clock()
+
+        def finish(r, status, steps, admitted, samples=None):
+            t = self.clock() - t0
+            results.append(Result(r.rid, r.model, r.system.n, status, steps, r.arrival, admitted, t, samples))
+            self.log.append((t, "done" if status == 0 else "failed", r.rid))
+
         while pending or running:
-            now = self.clock() - t0
-            while pending and pending[0].arrival <= now:
-                r = pending[0]
-                be = self.backends[r.model]
-                fp = be.footprint(r.system, r.precision)
-                if used + fp > self.budget:
-                    break
-                slot = be.admit(r.system, r.precision)
-                if slot is None:
-                    break
-                used += fp
-                running[(r.model, slot)] = (r, fp, self.clock() - t0)
-                pending.popleft()
-                self.log.append((self.clock() - t0, "admit", r.rid))
-            if not running:
-                wait = pending[0].arrival - (self.clock() - t0)
-                if wait > 0:
-                    self.sleep(wait)
-                continue
-            busy = [be for be in self.backends.values() if be.active()]
-            for be in busy:
-                be.step(self.chunk)
-            for be in busy:
-                be.sync()
+            progressed = False
+            # 1. completions of families whose chunk has finished
             for model, be in self.backends.items():
-                if not be.active():
+                if model not in inflight or not be.ready():
                     continue
+                inflight.discard(model)
+                progressed = True
                 for slot, steps, status, done in be.poll():
                     if not done:
                         continue
@@ -155,9 +156,59 @@ class Server:
                     samples = be.collect(slot) if self.keep_samples else None
                     be.retire(slot)
                     used -= fp
-                    t = self.clock() - t0
-                    results.append(Result(r.rid, model, r.system.n, status, steps, r.arrival, adm, t, samples))
-                    self.log.append((t, "done", r.rid))
+                    finish(r, status, steps, adm, samples)
+            # 2. admission in arrival order
+            now = self.clock() - t0
+            held = set()                      # families that keep their later requests back
+            keep: List[Request] = []
+            stop = False
+            for idx, r in enumerate(pending):
+                if stop or r.arrival > now:
+                    keep.extend(pending[idx:])
+                    break
+                if r.model in held:
+                    keep.append(r)
+                    continue
+                be = self.backends[r.model]
+                fp = be.footprint(r.system, r.precision)
+                if fp > self.budget:          # can never fit: fail it now
+                    finish(r, 2, 0, now)
+                    progressed = True
+                    continue
+                if used + fp > self.budget:   # the budget blocks everything behind it
+                    keep.extend(pending[idx:])
+                    break
+                if r.model in inflight:
+                    held.add(r.model)
+                    keep.append(r)
+                    continue
+                slot = be.admit(r.system, r.precision)
+                if slot is None:
+                    if not running and not inflight:   # nothing will ever free room for it
+                        finish(r, getattr(be, "last_status", 5) or 5, 0, now)
+                        progressed = True
+                        continue
+                    held.add(r.model)
+                    keep.append(r)
+                    continue
+                used += fp
+                running[(r.model, slot)] = (r, fp, self.clock() - t0)
+                self.log.append((self.clock() - t0, "admit", r.rid))
+                progressed = True
+            pending = keep
+            # 3. every idle family with work starts its next chunk
+            for model, be in self.backends.items():
+                if model not in inflight and be.active():
+                    be.launch(self.chunk)
+                    inflight.add(model)
+                    progressed = True
+            if not running and pending:
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0:
+                    self.sleep(wait)
+                continue
+            if not progressed:
+                self.sleep(self.poll_s)
         return results
 
 

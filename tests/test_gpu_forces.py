@@ -265,6 +265,46 @@ def test_argument_errors_are_reported_before_launch():
         ctx.forces(ew, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
 
 
+@pytest.mark.parametrize("bad_index", [-1, 3, 7])
+def test_a_bad_device_species_index_is_reported(bad_index):
+    """A species index outside the table in the caller's device array cannot
+    be checked before launch: the call's sums and that molecule's force turn
+    NaN, ms2_device_errors reports it once, and the next good call is clean."""
+    s = I.jittered(I.quadrupolar_fluid(n=200, density=0.6), 0.1, seed=31)
+    ctx = ms2.Context(s.species)
+    ctx.device_errors()                                  # nothing recorded yet
+    d = ms2.DeviceSystem(s)
+    d.species[17] = bad_index
+    say(f"[gpu] bad species index {bad_index} at molecule 17")
+    f, t, su = ms2.evaluate(ctx, s, ms2.FP32, dev=d)
+    assert np.isnan(su[:10]).all()
+    assert np.isnan(f[17]).all() and np.isfinite(np.delete(f, 17, axis=0)).all()
+    with pytest.raises(ms2.MS2Error) as e:
+        ctx.device_errors()
+    assert e.value.status == 1
+    ctx.device_errors()                                  # cleared by the check
+    d.species[17] = 0
+    f, t, su = ms2.evaluate(ctx, s, ms2.FP32, dev=d)
+    assert np.isfinite(su).all() and np.isfinite(f).all()
+    ctx.device_errors()
+
+
+def test_a_bad_device_species_index_poisons_the_reciprocal_sums():
+    s = small_system(ionic_pair_species(), 40, 4.8, 2.1, seed=5, elec=I.ELEC_EWALD, alpha=1.3, kmax2=20)
+    ctx = ms2.Context(s.species)
+    d = ms2.DeviceSystem(s)
+    p = ms2.params_struct(s.params, ms2.FP64)
+    ctx.forces(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    d.sums[:] = 0.0
+    d.species[3] = 9
+    say("[gpu] bad species index 9 at molecule 3, k-space only")
+    ctx.ewald_kspace(p, d.n, d.species, d.com, d.quat, d.force, d.torque, d.sums)
+    torch.cuda.synchronize()
+    assert math.isnan(d.sums[2].item())
+    with pytest.raises(ms2.MS2Error):
+        ctx.device_errors()
+
+
 # --------------------------------------------------------------------------
 # tile shapes: the work decomposition never changes the result beyond rounding
 # --------------------------------------------------------------------------

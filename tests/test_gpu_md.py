@@ -201,3 +201,39 @@ def test_admission_limits_and_slot_reuse():
     with pytest.raises(ms2.MS2Error) as e:
         b.admit(bad, ms2.FP32)
     assert e.value.status == 1
+
+
+def test_moment_sampling_is_refused_with_ewald():
+    """Z = d2U/dV2 has no reciprocal part, so Lustig moments are not offered
+    together with Ewald summation (Sec. 4): admission and the footprint query
+    refuse it; the same system without moments is admitted."""
+    s = I.ionic_solution(n_water=90, n_pairs=5, n_steps=3)
+    s.md.sample_every = 1
+    ctx = ms2.Context(s.species)
+    b = ms2.Batch(ctx, 1)
+    for call in (lambda: b.footprint(s, ms2.FP32), lambda: b.admit(s, ms2.FP32)):
+        with pytest.raises(ms2.MS2Error) as e:
+            call()
+        assert e.value.status == 1
+    s.md.sample_every = 0
+    slot = b.admit(s, ms2.FP32)
+    b.step(3)
+    assert b.status(slot) == (3, 0)
+
+
+def test_retired_slot_memory_is_reused():
+    """A retired slot's allocation serves a later admission of equal or
+    smaller size; results are unchanged by the reuse."""
+    s = I.quadrupolar_fluid(n=300, density=0.6, n_steps=20, sample_every=1)
+    small = I.quadrupolar_fluid(n=200, density=0.6, seed=4, n_steps=20, sample_every=1)
+    ctx = ms2.Context(s.species)
+    b = ms2.Batch(ctx, 2)
+    x = b.admit(s, ms2.FP32)
+    b.step(20)
+    b.retire(x)
+    y = b.admit(small, ms2.FP32)
+    b.step(20)
+    got = b.sample(y)
+    ref = run_gpu(small, ms2.FP32, 20)
+    for k in ("com", "quat", "vel", "omega", "moments", "sums"):
+        assert np.array_equal(ref[k], got[k]), k

@@ -188,3 +188,14 @@ def test_lustig_moments_match_the_per_step_sums():
     # virial route: dU/dV = -(W/(3V) + p_lrc)
     y0 = (su[US] + su[US_LRC]) / (3 * V)
     assert y0 == pytest.approx(-(su[VIR] / (3 * V) - su[US_LRC] / (3 * V)), rel=1e-12)
+
+
+def test_moment_sampling_with_ewald_is_refused():
+    """The oracle, like the library, offers no Lustig moments with Ewald
+    summation (Sec. 4): d2U/dV2 has no reciprocal part."""
+    s = small_system(ionic_pair_species(), 16, 4.0, 1.9, seed=2, elec=I.ELEC_EWALD, alpha=1.5, kmax2=10)
+    s.md = I.MDSettings(integrator=I.GEAR, dt=0.001, n_steps=2, sample_every=1)
+    with pytest.raises(ValueError):
+        oracle.md(s)
+    s.md.sample_every = 0
+    assert oracle.md(s)["log"].shape == (3, oracle.LOG_COLS)

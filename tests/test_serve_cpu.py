@@ -21,15 +21,18 @@ class FakeClock:
 
 
 class FakeBackend:
-    """Slots advance k steps per step(k); each chunk costs `cost` seconds of
-    the fake clock.  A request whose system has `fail_at` stops there with
-    status 4 (non-finite)."""
+    """Slots advance k steps per launch(k); the chunk is ready `cost` seconds
+    of the fake clock later (families' chunks overlap, as on the device's
+    streams).  A request whose system has `fail_at` stops there with status 4
+    (non-finite)."""
 
     def __init__(self, clock, max_slots=4, cost=0.01, bytes_per_mol=100):
         self.clock, self.max_slots, self.cost, self.bpm = clock, max_slots, cost, bytes_per_mol
         self.slots = {}
         self.peak_active = 0
         self.admitted = []
+        self.busy_until = 0.0
+        self.last_status = 5
 
     def footprint(self, system, precision):
         return system.n * self.bpm
@@ -46,7 +49,8 @@ class FakeBackend:
     def active(self):
         return len(self.slots)
 
-    def step(self, k):
+    def launch(self, k):
+        assert self.ready(), "a chunk was launched while the previous one was in flight"
         for s in self.slots.values():
             if s["status"] or s["steps"] >= s["sys"].md.n_steps:
                 continue
@@ -56,10 +60,10 @@ class FakeBackend:
                 s["steps"], s["status"] = fail, 4
             else:
                 s["steps"] = new
-        self.clock.t += self.cost
+        self.busy_until = self.clock.t + self.cost
 
-    def sync(self):
-        pass
+    def ready(self):
+        return self.clock.t >= self.busy_until
 
     def poll(self):
         return [(slot, s["steps"], s["status"], s["status"] != 0 or s["steps"] >= s["sys"].md.n_steps)
@@ -132,6 +136,39 @@ def test_two_model_families_share_the_budget():
     res = srv.run(reqs)
     assert len(res) == 8
     assert a.peak_active + b.peak_active <= 3 + 1
+
+
+def test_a_request_that_can_never_fit_fails_without_blocking_the_rest():
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=4)
+    srv = Server({"a": be}, hbm_budget=300 * 100, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    reqs = [req(0, 0.0), req(1, 0.001, n=400), req(2, 0.002), req(3, 0.003)]
+    res = {r.rid: r for r in srv.run(reqs)}
+    assert sorted(res) == [0, 1, 2, 3]
+    assert res[1].status == 2 and res[1].steps_done == 0 and 1 not in be.admitted
+    assert all(res[k].status == 0 and res[k].steps_done == 300 for k in (0, 2, 3))
+
+
+def test_a_request_refused_by_an_idle_backend_fails():
+    clk = FakeClock()
+    full = FakeBackend(clk, max_slots=0)
+    ok = FakeBackend(clk, max_slots=2)
+    srv = Server({"full": full, "ok": ok}, hbm_budget=10 ** 9, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    res = {r.rid: r for r in srv.run([req(0, 0.0, model="full"), req(1, 0.5, model="ok")])}
+    assert res[0].status == 5 and res[0].steps_done == 0
+    assert res[1].status == 0 and res[1].steps_done == 300
+
+
+def test_families_progress_independently():
+    """A request of a fast family arriving while a slow family's chunk is on
+    the device is admitted, run and finished before that chunk ends."""
+    clk = FakeClock()
+    slow, fast = FakeBackend(clk, cost=1.0), FakeBackend(clk, cost=0.01)
+    srv = Server({"slow": slow, "fast": fast}, hbm_budget=10 ** 9, chunk_steps=100, clock=clk, sleep=clk.sleep)
+    res = {r.rid: r for r in srv.run([req(0, 0.0, model="slow", steps=200), req(1, 0.1, model="fast", steps=300)])}
+    assert res[1].status == 0 and res[1].finished < 1.0
+    assert res[0].finished >= 2.0
+    assert res[1].admitted - res[1].arrival < 0.01
 
 
 def test_nearest_rank_percentiles():
