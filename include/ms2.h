@@ -37,6 +37,7 @@ extern "C" {
 
 #define MS2_MAX_SITES 8      /* sites per species            */
 #define MS2_MAX_SPECIES 8    /* species per context          */
+#define MS2_NOALLOC_MAX_MOL 4096  /* molecules per ms2_forces_noalloc call */
 
 typedef enum {
   MS2_OK = 0,
@@ -147,6 +148,22 @@ void ms2_destroy(ms2_ctx* ctx);
 ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
                       const int32_t* d_species, const double* d_com, const double* d_quat,
                       double* d_force, double* d_torque, double* d_sums, void* stream);
+
+/* ms2_forces for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, outputs, errors and device-side species check as
+ * ms2_forces, and the same result bit for bit as ms2_forces with its default
+ * tile shape (symmetric 64 x 64 tile pairs; this call always takes that
+ * shape).  It calls no hipMalloc/hipFree and allocates nothing: its scratch
+ * (site records, pair partials, block sums, work items; under 16 MiB) is a
+ * static device array that each GPU the library runs on holds until the
+ * process ends.  Limit: 2 <= n_mol <= MS2_NOALLOC_MAX_MOL, otherwise
+ * MS2_EINVAL before anything is enqueued.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on the same GPU (other streams, threads or
+ * contexts) race and must be serialized by the caller. */
+ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
+                              const int32_t* d_species, const double* d_com, const double* d_quat,
+                              double* d_force, double* d_torque, double* d_sums, void* stream);
 
 /* Ewald reciprocal-space part (Sec. 4): k = 2 pi n / L over the half space
  * of integer n with 0 < |n|^2 <= kmax2; S(k) = sum_a q_a exp(i k.r_a)

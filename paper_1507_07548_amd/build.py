@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libms2.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["forces.hip", "kspace.hip", "md.hip", "api.cpp", "batch.cpp", "autotune.cpp", "massieu.cpp"]
+SOURCES = ["forces.hip", "kspace.hip", "md.hip", "noalloc.hip", "api.cpp", "batch.cpp", "autotune.cpp", "massieu.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-I" + os.path.join(ROOT, "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -376,7 +376,7 @@ int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, i
 // ---------------------------------------------------------------------------
 // single-system calls: parameters travel through a ring of pinned blocks
 // ---------------------------------------------------------------------------
-static ms2_status ring_acquire(ms2_ctx* ctx, RingSlot** out) {
+ms2_status ring_acquire(ms2_ctx* ctx, RingSlot** out) {
   RingSlot& r = ctx->ring[ctx->ring_pos];
   ctx->ring_pos = (ctx->ring_pos + 1) % kRing;
   if (r.used) MS2_HIP(hipEventSynchronize(r.ev));
@@ -516,6 +516,7 @@ ms2_status ms2_create(ms2_ctx** out, const ms2_species* h_species, int32_t n_spe
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, &c->tab, sizeof(SpeciesTable), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(int));
+  if (e == hipSuccess) e = noalloc_scratch_attach(device);
   for (int k = 0; k < kRing && e == hipSuccess; ++k) {
     RingSlot& r = c->ring[k];
     e = hipHostMalloc((void**)&r.h_slot, sizeof(SlotDev), hipHostMallocDefault);

@@ -43,6 +43,21 @@ hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const 
 hipError_t launch_rdf(int waves, const WorkItem* items, int base, int count, const SlotDev* slots,
                       const MDDev* md, const SysParams* prm, const SpeciesTable* tab,
                       hipStream_t st);
+
+// number of half-space k vectors with 0 < |n|^2 <= kmax2
+int kvec_count(int kmax2) {
+  const int m = (int)std::floor(std::sqrt((double)kmax2));
+  int c = 0;
+  for (int x = 0; x <= m; ++x)
+    for (int y = -m; y <= m; ++y)
+      for (int z = -m; z <= m; ++z) {
+        const int n2 = x * x + y * y + z * z;
+        if (n2 == 0 || n2 > kmax2) continue;
+        if (x == 0 && (y < 0 || (y == 0 && z < 0))) continue;
+        c++;
+      }
+  return c;
+}
 }  // namespace ms2
 
 using namespace ms2;
@@ -128,19 +143,6 @@ SlotLayout layout_of(const SlotShape& s) {
   return L;
 }
 
-int kvec_count(int kmax2) {
-  const int m = (int)std::floor(std::sqrt((double)kmax2));
-  int c = 0;
-  for (int x = 0; x <= m; ++x)
-    for (int y = -m; y <= m; ++y)
-      for (int z = -m; z <= m; ++z) {
-        const int n2 = x * x + y * y + z * z;
-        if (n2 == 0 || n2 > kmax2) continue;
-        if (x == 0 && (y < 0 || (y == 0 && z < 0))) continue;
-        c++;
-      }
-  return c;
-}
 
 }  // namespace
 

@@ -71,4 +71,11 @@ int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, i
 // true when the pair kernels may take their single-species form: one species,
 // with at least one site of every kind its model class holds
 bool single_species_form(const ms2_ctx* ctx);
+int kvec_count(int kmax2);
+// next block of the context's ring of pinned parameter blocks (waits for
+// the call that used it last)
+ms2_status ring_acquire(ms2_ctx* ctx, RingSlot** out);
+// device address of the no-allocation scratch array on the current device
+// (looked up once per device; ms2_create calls it with its device current)
+hipError_t noalloc_scratch_attach(int device);
 }  // namespace ms2

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libms2.so")
 
 MAX_SITES = 8
 MAX_SPECIES = 8
+NOALLOC_MAX_MOL = 4096
 NSUM = 12
 SUM_NAMES = ["u_lj", "u_elec", "u_recip", "u_const", "u_lrc", "virial", "us", "uss",
              "us_lrc", "uss_lrc", "npair", "nsite"]
@@ -84,7 +85,7 @@ EXPORTED = ["ms2_create", "ms2_destroy", "ms2_forces", "ms2_ewald_kspace", "ms2_
             "ms2_batch_destroy", "ms2_slot_footprint", "ms2_slot_admit", "ms2_slot_retire",
             "ms2_step", "ms2_sample", "ms2_slot_status", "ms2_tile_config", "ms2_set_tile_config",
             "ms2_autotune", "ms2_batch_timing", "ms2_massieu", "ms2_massieu_properties",
-            "ms2_device_errors", "ms2_last_error"]
+            "ms2_device_errors", "ms2_forces_noalloc", "ms2_last_error"]
 
 
 def lib():
@@ -98,7 +99,7 @@ def lib():
         L.ms2_create.argtypes = [P(vp), P(Species), c_int32, c_int32]
         L.ms2_destroy.argtypes = [vp]
         L.ms2_destroy.restype = None
-        for fn in (L.ms2_forces, L.ms2_ewald_kspace):
+        for fn in (L.ms2_forces, L.ms2_ewald_kspace, L.ms2_forces_noalloc):
             fn.argtypes = [vp, P(Params), c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.ms2_device_errors.argtypes = [vp, vp]
         L.ms2_batch_create.argtypes = [vp, c_int32, c_size_t, c_int32, P(vp)]
@@ -190,6 +191,13 @@ class Context:
         check(lib().ms2_forces(self.handle, ctypes.byref(params), n, species.data_ptr(), com.data_ptr(),
                                quat.data_ptr(), force.data_ptr(), torque.data_ptr(), sums.data_ptr(),
                                _stream_ptr(stream)))
+
+    def forces_noalloc(self, params: Params, n: int, species, com, quat, force, torque, sums, stream=None):
+        """ms2_forces_noalloc: ms2_forces with its scratch in the library's
+        static device array (n <= MS2_NOALLOC_MAX_MOL)."""
+        check(lib().ms2_forces_noalloc(self.handle, ctypes.byref(params), n, species.data_ptr(),
+                                       com.data_ptr(), quat.data_ptr(), force.data_ptr(), torque.data_ptr(),
+                                       sums.data_ptr(), _stream_ptr(stream)))
 
     def ewald_kspace(self, params: Params, n: int, species, com, quat, force, torque, sums, stream=None):
         check(lib().ms2_ewald_kspace(self.handle, ctypes.byref(params), n, species.data_ptr(),
