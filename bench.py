@@ -11,17 +11,22 @@ corrector, isokinetic thermostat, Lustig moment sums):
   FP32 site arithmetic with FP64 accumulation, moments every step, all
   systems resident on the GPU and advanced by one hipGraph per K steps.
 
-Printed JSON line: site-pair interactions/s of the batched form (value), MD
-steps/s, the plain one-system-per-launch form on a sample of the same
-systems, the same batched workload in FP64, the ionic-solution system with
-Ewald (real-space and reciprocal calls timed apart, and its MD step rate), a
-serving trace (p50/p99 latency), the pair kernel's roofline (HIP events
-around its launches inside the timed graph) and the oracle timed on the host
+Printed JSON line: site-pair interactions/s of the batched form (value; the
+median of five timed windows of K steps), MD steps/s, the plain
+one-system-per-launch form on the same 256 systems, the same batched
+workload in FP64, the ionic-solution system with Ewald (real-space and
+reciprocal calls timed apart, and its MD step rate), the serving form at its
+configured request size (2e4 steps, 1000-step ACF window) with a second run
+at 0.7 x the measured capacity, the pair kernel's roofline (HIP events around
+its launches inside the timed graph) and the oracle timed on the host cores
 as a CPU baseline.
+
+--case NAME runs one small batch only (a lone system advanced K steps by
+graph replay) and prints its step time: the launch-gap traces of the
+persistent-kernel decision are taken with it.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,13 +34,26 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 operations per site-pair evaluation (force on both
-# molecules via Newton's third law, energy, virial, dU/ds and d2U/ds2), with
-# a fused multiply-add counted as 2 and rcp/rsqrt as 1.
+# Algorithmic FP32 operations (a fused multiply-add counts 2, rcp / rsqrt 1)
+# of one 2CLJQ molecule pair, counted from the site-pair formulas:
+#   LJ site pair   48: separation 6, |r|^2 5, 1/r^2 1, powers and c6, c12
+#                      terms 5, u and its sum 2, u'/r 4, force 3, the two
+#                      sites' force sums 6 (32); d2U/ds2: r.R 5, u'' 4, the
+#                      combination 6, its sum 1 (16)
+#   QQ site pair  122: 1/R 1, n 3, three cosines 15, P 16, its three
+#                      partial derivatives 19, R^-5 3, prefactor 1, u and its
+#                      sum 2, force 24, the two orientation gradients 24,
+#                      their sums and the force sums 12, d2U/ds2 and its sum 2
+#   molecule pair  21: the pair force summed over its 5 site pairs 15,
+#                      dU/ds = -R.F 5 and its sum 1
 FLOP_LJ = 48
-FLOP_QQ = 189
-PEAK_FP32_VALU = 157.3e12     # MI355X dense FP32 vector (packed) FLOP/s
+FLOP_QQ = 122
+FLOP_MOL = 21
+FLOP_PER_MOL_PAIR = 4 * FLOP_LJ + FLOP_QQ + FLOP_MOL        # 335
+PEAK_FP32_VALU = 157.3e12     # MI355X dense FP32 vector FLOP/s (packed FP32)
+PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 instructions (not used by this build)
 METRIC = "site-pair interactions/s and MD steps/s (batched vs plain) at 1 GPU; p50/p99 latency"
+WINDOWS = 5
 
 
 def log(*a):
@@ -51,86 +69,143 @@ def kernel_label(tuned):
     return " + ".join(names)
 
 
-def cpu_baseline(systems, budget_s=12.0):
-    """The FP64 oracle (single thread) on a bounded sample of the same state
-    points: Gear NVT steps with moment sampling, site pairs per second."""
+def host_cpu():
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def _oracle_worker(args):
+    """One host process: the oracle's Gear NVT with moment sampling on one
+    state point (1 initial evaluation + `steps` steps); returns (site pairs,
+    seconds)."""
+    s_index, steps = args
     import oracle
-    t_total, sp_total, used = 0.0, 0.0, []
-    for s in systems:
-        x = s.copy()
-        x.md.n_steps = 2
-        _, _, sums = oracle.forces(x)
-        t0 = time.perf_counter()
-        oracle.md(x, want_log=False)
-        dt = time.perf_counter() - t0
-        t_total += dt
-        sp_total += sums[11] * (x.md.n_steps + 1)   # initial evaluation + one per step
-        used.append(s.n)
-        if t_total > budget_s:
-            break
-    return {"value": sp_total / t_total, "unit": "site-pair interactions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(used)} state points (N={used}) x (1 initial + 2 Gear NVT steps) in FP64, "
-                      f"single thread, {t_total:.1f} s"}
+    from paper_1507_07548_amd import inputs
+    s = inputs.batched_state_point(s_index)
+    s.md.n_steps = steps
+    _, _, sums = oracle.forces(s)
+    t0 = time.perf_counter()
+    oracle.md(s, want_log=False)
+    return sums[11] * (steps + 1), time.perf_counter() - t0
 
 
-def serve_trace(n_requests, n_steps):
-    """The serving form on a scaled trace of the mixed-model workload:
-    Poisson arrivals at 50/s, models uniform over {one-site LJ, 2CLJQ,
-    water + 10 % ions with Ewald}, N log-uniform in [256, 8192], each request
-    running `n_steps` steps (the full workload asks 2e4) with RDF (400 bins),
-    Lustig moments (non-Ewald) and velocity/current ACFs over a 200-step
-    window on an extended step of 10."""
+def cpu_baseline(max_procs=16, steps=8):
+    """The FP64 oracle as it stands (one thread per process) on the host
+    cores: one process per state point of a fixed sample (state points
+    0..P-1 of the same workload), all running at once; site pairs of the
+    sample / wall time.  The single-process rate is reported beside it."""
+    import multiprocessing as mp
+    model, avail = host_cpu()
+    procs = max(1, min(max_procs, avail))
+    jobs = [(k, steps) for k in range(procs)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    sp = sum(r[0] for r in res)
+    single = sum(r[0] for r in res) / sum(r[1] for r in res)
+    return {"value": sp / wall, "unit": "site-pair interactions/s", "cores": procs, "kind": "oracle",
+            "sample": f"state points 0..{procs - 1} of the batched workload (FP64 oracle, Gear NVT with "
+                      f"moments, 1 initial evaluation + {steps} steps each), one single-threaded oracle "
+                      f"process per state point on {procs} host cores at once, {wall:.1f} s wall",
+            "single_thread_value": single, "host_cpu": model, "host_cpus_available": avail}
+
+
+def serve_run(n_requests, n_steps, rate, window, label):
+    """The serving form: Poisson arrivals, models uniform over {one-site LJ,
+    2CLJQ, water + 10 % ions with Ewald}, N log-uniform in [256, 8192], each
+    request running `n_steps` steps with RDF (400 bins), Lustig moments
+    (non-Ewald) and velocity/current ACFs over a `window`-step window on an
+    extended step of 10."""
     import torch
 
     from paper_1507_07548_amd import inputs, ms2
     from paper_1507_07548_amd.serve import GpuBackend, Request, Server, percentile
-    trace = inputs.serving_trace(n_requests=n_requests, rate=50.0, seed=5, n_steps=n_steps,
-                                 window=200, acf_every=10, origin_every=50)
+    trace = inputs.serving_trace(n_requests=n_requests, rate=rate, seed=5, n_steps=n_steps,
+                                 window=window, acf_every=10, origin_every=100 if window >= 1000 else 50)
     fam = {"lj": [inputs.one_center_lj()], "2cljq": [inputs.two_center_lj_quadrupole()],
            "ionic": [inputs.water_tip4p_like(), inputs.cation(), inputs.anion()]}
     backends = {m: GpuBackend(fam[m], max_slots=64) for m in fam}
     reqs = [Request(r, t, m, s, ms2.FP32) for r, (t, m, s) in enumerate(trace)]
-    log(f"[bench] serving {len(reqs)} requests x {n_steps} steps")
+    log(f"[bench] serving ({label}): {len(reqs)} requests x {n_steps} steps at {rate:.3g}/s")
     srv = Server(backends, hbm_budget=64 << 30, chunk_steps=50, keep_samples=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = srv.run(reqs)
     makespan = time.perf_counter() - t0
+    for be in backends.values():
+        be.batch.close()
+        be.ctx.close()
     lat = [r.latency for r in res]
     steps = sum(r.steps_done for r in res)
-    ok = all(r.status == 0 for r in res)
-    return {"requests": len(res), "steps_per_request": n_steps, "arrival_rate_per_s": 50.0,
-            "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
-            "md_steps_per_s": steps / makespan, "makespan_s": makespan, "all_ok": ok,
-            "n_range": [256, 8192], "models": ["1CLJ (VV NVE)", "2CLJQ (Gear NVT, RF)",
-                                              "water+ions (Gear NVT, Ewald)"],
-            "note": "scaled trace: the full request asks 2e4 steps and a 1000-step ACF window"}
+    return {"requests": len(res), "steps_per_request": n_steps, "acf_window_steps": window,
+            "arrival_rate_per_s": rate, "p50_latency_s": percentile(lat, 50),
+            "p99_latency_s": percentile(lat, 99), "md_steps_per_s": steps / makespan,
+            "makespan_s": makespan, "all_ok": all(r.status == 0 for r in res), "n_range": [256, 8192]}
+
+
+def serving(n_requests, n_steps, window, sustained_requests, scaled):
+    """Two runs at the configured request size: the workload's own trace at
+    50 requests/s (an overload: latency includes queueing), then a run at
+    0.7 x the capacity that run measured (system-steps/s / steps per
+    request); plus, optionally, the short-request trace of earlier versions."""
+    out = {"models": ["1CLJ (VV NVE)", "2CLJQ (Gear NVT, RF)", "water+ions (Gear NVT, Ewald)"]}
+    full = serve_run(n_requests, n_steps, 50.0, window, "trace at 50/s")
+    capacity = full["md_steps_per_s"] / n_steps
+    out["trace_50_per_s"] = full
+    out["capacity_requests_per_s"] = capacity
+    if sustained_requests > 0:
+        out["sustained_0p7_capacity"] = serve_run(sustained_requests, n_steps, 0.7 * capacity, window,
+                                                  "0.7 x capacity")
+    if scaled:
+        sc = serve_run(n_requests, 400, 50.0, 200, "scaled")
+        sc["note"] = "scaled requests (400 steps, 200-step window), kept for comparison with earlier lines"
+        out["scaled_400_steps"] = sc
+    return out
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pair_sym_kernel_hbm_traffic.md")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "pair_sym_kernel_sq_counters.md")
 
 
-def recorded_traffic():
-    """HBM bytes per batched pair-kernel launch from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
-    from paper_1507_07548_amd.rocprof_summary import pair_kernel_source_hash
-    if not os.path.exists(TRAFFIC_SUMMARY):
-        return None
+def _summary_fields(path):
     fields = {}
-    for ln in open(TRAFFIC_SUMMARY):
-        if ln.startswith("- ") and ": " in ln:
-            k, v = ln[2:].strip().split(": ", 1)
-            fields[k] = v.strip("` ")
-    if fields.get("source_sha256") != pair_kernel_source_hash():
+    if os.path.exists(path):
+        for ln in open(path):
+            if ln.startswith("- ") and ": " in ln:
+                k, v = ln[2:].strip().split(": ", 1)
+                fields[k] = v.strip("` ")
+    return fields
+
+
+def recorded(path, key):
+    """A figure from a committed counter summary, or None when the pair
+    kernel's sources changed since the counters were taken."""
+    from paper_1507_07548_amd.rocprof_summary import pair_kernel_source_hash
+    f = _summary_fields(path)
+    if key not in f or f.get("source_sha256") != pair_kernel_source_hash():
         return None
-    return float(fields["hbm_bytes_per_launch"])
+    return float(f[key])
 
 
-def plain_form(ms2, torch, ctx, sample, K, W):
-    """One system per launch, no graph, plain tile shapes."""
-    log(f"[bench] plain form on {len(sample)} systems")
+def plain_form(ms2, torch, ctx, systems, K, W):
+    """One system per launch, no graph, plain tile shapes: every state point
+    of the batched workload, one after the other."""
+    log(f"[bench] plain form on {len(systems)} systems")
     batches = []
-    for s in sample:
+    for s in systems:
         b = ms2.Batch(ctx, 1, plain_tiles=True)
         b.admit(s, ms2.FP32)
         b.step(W if W > 0 else 1, graph=False)
@@ -146,8 +221,8 @@ def plain_form(ms2, torch, ctx, sample, K, W):
     sp = sum(a["site_pairs_total"] - b["site_pairs_total"] for a, b in zip(pa, pb))
     for b in batches:
         b.close()
-    return {"value": sp / (t1 - t0), "md_steps_per_s": len(sample) * K / (t1 - t0), "systems": len(sample),
-            "form": "one system per launch, no graph, plain tile shapes"}
+    return {"value": sp / (t1 - t0), "md_steps_per_s": len(systems) * K / (t1 - t0), "systems": len(systems),
+            "form": "one system per launch, no graph, plain tile shapes, the same state points"}
 
 
 def precision_form(ms2, torch, ctx, systems, K, W, graph):
@@ -218,20 +293,58 @@ def ionic_form(ms2, torch, inputs, K, W):
                     "ms2_ewald_kspace (FP64); MD step = Gear NVT + RDF every 10 steps, graph"}
 
 
+CASES = {
+    # lone systems of the serving mix, advanced by graph replay (FP32)
+    "lone_2cljq_256": lambda I: I.quadrupolar_fluid(n=256, density=0.6),
+    "lone_2cljq_1000": lambda I: I.quadrupolar_fluid(n=1000, density=0.6),
+    "lone_ionic_1000": lambda I: I.ionic_solution(),
+}
+
+
+def run_case(name, K, W):
+    """One lone system advanced K steps by graph replay; prints its step time."""
+    import torch
+
+    from paper_1507_07548_amd import inputs, ms2
+    s = CASES[name](inputs)
+    s.md.n_steps = W + 2 * K + 10
+    ctx = ms2.Context(s.species)
+    b = ms2.Batch(ctx, 1)
+    slot = b.admit(s, ms2.FP32)
+    b.step(max(W, 1), graph=True)
+    b.step(K, graph=True, prepare=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(K, graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = b.sample(slot, state=False)
+    assert out["status"] == 0
+    b.close()
+    ctx.close()
+    print(json.dumps({"case": name, "molecules": s.n, "steps": K, "ms_per_step": (t1 - t0) / K * 1e3}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--systems", type=int, default=256)
-    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--plain-systems", type=int, default=-1,
+                    help="state points of the plain form (default: all of the batched ones)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form of the batched workload")
     ap.add_argument("--no-ewald", action="store_true", help="skip the ionic-solution (Ewald) timing")
-    ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--serve-steps", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=20000)
+    ap.add_argument("--serve-window", type=int, default=1000)
+    ap.add_argument("--serve-sustained-requests", type=int, default=24)
+    ap.add_argument("--serve-scaled", action="store_true", help="also run the 400-step request trace")
+    ap.add_argument("--windows", type=int, default=WINDOWS, help="timed windows of K steps (median reported)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the batched steps directly instead of through a hipGraph")
     ap.add_argument("--tile-shape", type=str, default=None,
@@ -240,18 +353,30 @@ def main():
                     help="sample the heat-flux ACF (extended step 10, origins every 100, 100 lags) on every system")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel for HBM counters)")
+    ap.add_argument("--case", type=str, default=None, choices=sorted(CASES),
+                    help="run only this lone-system batch and print its step time")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every system runs on a single MI355X and "
               "sharding systems across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    K, W = args.steps, args.warmup
+    if args.case:
+        run_case(args.case, K, W)
+        return
+    # the host baseline runs first: its worker processes start before this
+    # process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle on the host cores)")
+        cpu = cpu_baseline()
+
     import torch
 
     from paper_1507_07548_amd import inputs, ms2
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    K, W = args.steps, args.warmup
     graph = not args.no_graph
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -282,7 +407,7 @@ def main():
         tuned = {f"{int(r[1])}": list(ctx.tile_config(int(r[1]), ms2.FP32, mode=1))
                  for r in rows if r[0] == 1}
 
-    # ---------------- batched form ----------------
+    # ---------------- batched form: the median of several K-step windows ----------------
     log(f"[bench] admitting {len(systems)} state points")
     batch = ms2.Batch(ctx, len(systems))
     slots = [batch.admit(s, ms2.FP32) for s in systems]
@@ -291,31 +416,38 @@ def main():
     if graph:
         batch.step(K, graph=True, timing=True, prepare=True)    # capture + instantiate, no run
     torch.cuda.synchronize()
-    before = [batch.sample(s, state=False) for s in slots]
-    log(f"[bench] timing {K} batched steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(K, graph=graph, timing=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    after = [batch.sample(s, state=False) for s in slots]
-    pair_ms, timed = batch.pair_time_ms()
-    dt = t1 - t0
-    site_pairs = sum(a["site_pairs_total"] - b["site_pairs_total"] for a, b in zip(after, before))
-    mol_pairs = sum(a["pairs_total"] - b["pairs_total"] for a, b in zip(after, before))
-    assert all(a["status"] == 0 and a["steps_done"] == b["steps_done"] + K for a, b in zip(after, before))
-    value = site_pairs / dt
-    steps_per_s = len(systems) * K / dt
-    flops_per_launch = (4 * FLOP_LJ + FLOP_QQ) * mol_pairs / K
-    pair_ms_avg = pair_ms / timed
-    achieved = flops_per_launch / (pair_ms_avg * 1e-3)
+    windows = []
+    for wi in range(args.windows):
+        before = [batch.sample(s, state=False) for s in slots]
+        log(f"[bench] timing {K} batched steps (window {wi + 1} of {args.windows})")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(K, graph=graph, timing=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        after = [batch.sample(s, state=False) for s in slots]
+        pair_ms, timed = batch.pair_time_ms()
+        assert all(a["status"] == 0 and a["steps_done"] == b["steps_done"] + K for a, b in zip(after, before))
+        windows.append({"dt": t1 - t0, "pair_ms_avg": pair_ms / timed,
+                        "site_pairs": sum(a["site_pairs_total"] - b["site_pairs_total"] for a, b in zip(after, before)),
+                        "mol_pairs": sum(a["pairs_total"] - b["pairs_total"] for a, b in zip(after, before))})
     batch.close()
+    med = sorted(windows, key=lambda w: w["dt"])[len(windows) // 2]
+    dt = med["dt"]
+    value = med["site_pairs"] / dt
+    steps_per_s = len(systems) * K / dt
+    mol_pairs_per_launch = med["mol_pairs"] / K
+    pair_ms_avg = med["pair_ms_avg"]
+    achieved = FLOP_PER_MOL_PAIR * mol_pairs_per_launch / (pair_ms_avg * 1e-3)
+    executed = recorded(SQ_SUMMARY, "fp32_flop_per_mol_pair_executed")
 
-    sample = systems[: args.plain_sample]
-    plain = plain_form(ms2, torch, ctx, sample, K, W) if sample else None
+    plain_n = len(systems) if args.plain_systems < 0 else args.plain_systems
+    plain = plain_form(ms2, torch, ctx, systems[:plain_n], K, W) if plain_n > 0 else None
     fp64 = None if args.no_fp64 else precision_form(ms2, torch, ctx, systems, K, W, graph)
     ewald = None if args.no_ewald else ionic_form(ms2, torch, inputs, K, W)
-    serving = None if args.no_serve else serve_trace(args.serve_requests, args.serve_steps)
+    ctx.close()
+    serve = None if args.no_serve else serving(args.serve_requests, args.serve_steps, args.serve_window,
+                                               args.serve_sustained_requests, args.serve_scaled)
 
     line = {
         "metric": METRIC,
@@ -336,14 +468,23 @@ def main():
                    "precision": "fp32 pairs, fp64 sums", "integrator": "gear-5 quaternion NVT",
                    "moments_every": 1, "graph": graph, "tile_shapes_batched": tuned,
                    "heat_flux_acf": bool(args.heat_flux)},
+        "timing": {"windows": len(windows), "window_ms_per_step": [w["dt"] / K * 1e3 for w in windows],
+                   "reported": "median window"},
         "md_steps_per_s": steps_per_s,
-        "mol_pairs_per_step": mol_pairs / K,
-        "site_pairs_per_step": site_pairs / K,
+        "mol_pairs_per_step": mol_pairs_per_launch,
+        "site_pairs_per_step": med["site_pairs"] / K,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": recorded_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": recorded(TRAFFIC_SUMMARY, "hbm_bytes_per_launch"),
+                     "traffic_source": "profiles/pair_sym_kernel_hbm_traffic.md (rocprofv3 --pmc FETCH_SIZE, "
+                                       "WRITE_SIZE, copy-calibrated; null once the kernel sources changed)",
                      "kernel": kernel_label(tuned),
                      "kernel_avg_ms": pair_ms_avg,
-                     "flop_per_mol_pair": 4 * FLOP_LJ + FLOP_QQ},
+                     "flop_per_mol_pair_algorithmic": FLOP_PER_MOL_PAIR,
+                     "flop_per_mol_pair_executed": executed,
+                     "frac_executed": (executed * mol_pairs_per_launch / (pair_ms_avg * 1e-3) / PEAK_FP32_VALU
+                                       if executed else None),
+                     "frac_of_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED},
     }
     if plain is not None:
         line["plain"] = plain
@@ -352,11 +493,10 @@ def main():
         line["fp64"] = fp64
     if ewald is not None:
         line["ewald"] = ewald
-    if serving is not None:
-        line["serving"] = serving
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(systems)
+    if serve is not None:
+        line["serving"] = serve
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -430,6 +430,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   const int kchunks = (nk + kKChunk - 1) / kKChunk;
   const int mtiles = (n + kMolTile - 1) / kMolTile;
   MS2_HIP(ctx->s_sites.ensure((size_t)class_reals(ctx->cls) * npad * rs));
+  if (p->cutoff_mode == MS2_CUT_SITE) MS2_HIP(ctx->s_lj64.ensure((size_t)3 * class_lj(ctx->cls) * npad * 8));
   MS2_HIP(ctx->s_pf.ensure((size_t)js * 6 * npad * 8));
   MS2_HIP(ctx->s_bsum.ensure((size_t)nitems * kNumBlockSums * 8));
   if (nk) {
@@ -459,6 +460,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   d.com = d_com;
   d.quat = d_quat;
   d.sites = ctx->s_sites.p;
+  d.lj64 = p->cutoff_mode == MS2_CUT_SITE ? (double*)ctx->s_lj64.p : nullptr;
   d.pf = ctx->s_pf.p;
   d.pf_single = p->precision == MS2_FP32 ? 1 : 0;
   d.bsum = (double*)ctx->s_bsum.p;
@@ -549,6 +551,7 @@ void ms2_destroy(ms2_ctx* c) {
   if (c->d_tab) (void)hipFree(c->d_tab);
   if (c->d_err) (void)hipFree(c->d_err);
   c->s_sites.release();
+  c->s_lj64.release();
   c->s_pf.release();
   c->s_bsum.release();
   c->s_skp.release();

@@ -72,7 +72,7 @@ namespace {
 
 // byte layout of one slot's allocation
 struct SlotLayout {
-  size_t species, sites, pf, bsum, force, torque, sums, r, q, w, vel;
+  size_t species, sites, lj64, pf, bsum, force, torque, sums, r, q, w, vel;
   size_t skp, sk, fk, kred, ksum, moments, md_part, rdf, acf_v, acf_j, acf_cnt, origin_v, origin_j,
       origin_t0;
   size_t res_idx, res_state, res_n0, res_part, res_inside, res_acf, res_cnt;
@@ -101,6 +101,7 @@ SlotLayout layout_of(const SlotShape& s) {
   const size_t n = s.n, np = s.npad, rs = s.precision == MS2_FP32 ? 4 : 8;
   L.species = take(n * 4);
   L.sites = take((size_t)class_reals(s.cls) * np * rs);
+  L.lj64 = take(s.site_cut ? (size_t)3 * class_lj(s.cls) * np * 8 : 0);
   L.pf = take((size_t)s.jsplits * 6 * np * rs);
   L.bsum = take((size_t)s.nitems * kNumBlockSums * 8);
   L.force = take(3 * n * 8);
@@ -526,6 +527,7 @@ ms2_status ms2_slot_admit(ms2_batch* b, const ms2_system* sys, int32_t* slot_out
   d.com = (const double*)(base + lay.r);
   d.quat = (const double*)(base + lay.q);
   d.sites = base + lay.sites;
+  d.lj64 = shape.site_cut ? (double*)(base + lay.lj64) : nullptr;
   d.pf = base + lay.pf;
   d.pf_single = shape.precision == MS2_FP32 ? 1 : 0;
   if (shape.heat_flux) {

@@ -52,7 +52,7 @@ struct ms2_ctx {
   ms2::SpeciesTable* d_tab = nullptr;
   int* d_err = nullptr;    // device error word of the single-system entry points
   // scratch of the single-system entry points
-  ms2::DevBuf s_sites, s_pf, s_bsum, s_skp, s_sk, s_fk, s_kred, s_ksum;
+  ms2::DevBuf s_sites, s_lj64, s_pf, s_bsum, s_skp, s_sk, s_fk, s_kred, s_ksum;
   std::map<int, std::pair<ms2::DevBuf, int>> kvecs;            // kmax2 -> (table, count)
   std::map<std::tuple<int, int, int>, ms2::CachedItems> item_cache;
   std::map<std::tuple<int, int, int>, ms2::TileCfg> tuned;     // (mode, precision, log2 n) -> shape

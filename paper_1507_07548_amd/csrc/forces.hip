@@ -28,6 +28,13 @@
 
 namespace ms2 {
 
+// One component of A b, rounded exactly as written (no fused multiply-add):
+// equal bit for bit to a plain FP64 evaluation of the same sum.
+__device__ __forceinline__ double rotate_row(const double* a, const double* b) {
+#pragma clang fp contract(off)
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
 // ---------------------------------------------------------------------------
 // Site frame: d = A(q) b and e = A(q) ehat for every site of every molecule.
 // Record layout per class: [lj 3*NLJ][ch 3*NCH][dp 6*NDP][qd 6*NQD], each
@@ -51,13 +58,21 @@ __global__ __launch_bounds__(256) void site_frame_kernel(const SlotDev* __restri
   int k = 0;
   auto put = [&](const double* b, int valid) {
     for (int c = 0; c < 3; ++c) {
-      double v = valid ? A[c][0] * b[0] + A[c][1] * b[1] + A[c][2] * b[2] : 0.0;
+      double v = valid ? rotate_row(A[c], b) : 0.0;
       out[(k + c) * np + i] = (Real)v;
     }
     k += 3;
   };
 #pragma unroll
   for (int a = 0; a < S.lj; ++a) put(D.lj_pos[a < D.nlj ? a : 0], a < D.nlj);
+  if (sd.lj64) {
+    // site-site cut-off: the LJ-site offsets in FP64 as well, for the
+    // decision r_ab^2 < rc^2 (taken in FP64 whatever the pair precision)
+#pragma unroll
+    for (int a = 0; a < S.lj; ++a)
+      for (int c = 0; c < 3; ++c)
+        sd.lj64[(3 * a + c) * np + i] = a < D.nlj ? rotate_row(A[c], D.lj_pos[a]) : 0.0;
+  }
 #pragma unroll
   for (int a = 0; a < S.ch; ++a) put(D.ch_pos[a < D.nch ? a : 0], a < D.nch);
 #pragma unroll
@@ -97,7 +112,7 @@ __device__ __forceinline__ ElecParams<Real> elec_params(const SysParams& P) {
   E.alpha = (Real)P.alpha;
   E.alpha2 = (Real)P.alpha2;
   E.gpref = (Real)P.gpref;
-  E.inv_ke = (Real)P.inv_ke;
+  E.inv_ke = P.inv_ke;
   return E;
 }
 
@@ -231,7 +246,7 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
       double dx, dy, dz, r2d;
       min_image(xi, yi, zi, s_com[0][jj], s_com[1][jj], s_com[2][jj], L, invL, dx, dy, dz, r2d);
       const Real Rx = (Real)dx, Ry = (Real)dy, Rz = (Real)dz;
-      const Real R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+      const Real R2 = (Real)r2d;
       PairAcc<Real> acc{0, 0, 0, 0, 0, 0};
       eval_molecule_pair<Real, C, false, TJ>(rec, &s_site[0][jj], spi, spj, s_tab, E, Rx, Ry, Rz, R2, ai,
                                              unused, acc);
@@ -334,7 +349,7 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <typename Real, int NR, bool HF>
+template <typename Real, int NR, bool HF, int NL64>
 struct SymTiles {
   // centres [xyz][molecule] of the columns, then the rows: phase 1 reads
   // three columns' components at offsets of one base address
@@ -344,6 +359,7 @@ struct SymTiles {
   Real stage[kSymWaves][9][64];         // F_i, tau_i, tau_j of each lane's pair
   unsigned char er[kSymWaves][kKeepDiags][64];  // row m's entry index on the chunk's k-th diagonal, or 255
   Real kin[HF ? 2 : 1][6][HF ? 64 : 1]; // heat flux: lab v and w of rows, columns
+  double lj64[NL64 ? 2 : 1][NL64 ? NL64 : 1][NL64 ? 64 : 1];  // site-site cut-off: FP64 LJ offsets
 };
 
 template <typename Real>
@@ -375,8 +391,9 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   constexpr int NR = class_reals(C);
   constexpr int TJ = 64, NW = kSymWaves;
 
+  constexpr int NL64 = SITE ? 3 * kClassShapes[C].lj : 0;
   __shared__ union {
-    SymTiles<Real, NR, HF> t;
+    SymTiles<Real, NR, HF, NL64> t;
     SymFinal<Real> f;
   } u;
   __shared__ int s_sp[ONE ? 1 : 2][ONE ? 1 : TJ];   // species of rows, columns (not read when ONE)
@@ -432,6 +449,13 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
       for (int k = 0; k < NR; ++k) r[k] = gsite[k * np + mc];
 #pragma unroll
       for (int k = 0; k < NR; ++k) u.t.site[side][k][lane] = r[k];
+      if constexpr (SITE) {
+        double l[NL64];
+#pragma unroll
+        for (int k = 0; k < NL64; ++k) l[k] = sd.lj64[k * np + mc];
+#pragma unroll
+        for (int k = 0; k < NL64; ++k) u.t.lj64[side][k][lane] = l[k];
+      }
     }
     if constexpr (HF) {
       if (wv < 2) {
@@ -526,7 +550,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     min_image(u.t.comi[0][row], u.t.comi[1][row], u.t.comi[2][row], u.t.comj[0][col], u.t.comj[1][col],
               u.t.comj[2][col], L, invL, dx, dy, dz, r2d);
     const Real Rx = (Real)dx, Ry = (Real)dy, Rz = (Real)dz;
-    const Real R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const Real R2 = (Real)r2d;
     Real rec[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) rec[k] = u.t.site[0][k][row];
@@ -536,8 +560,10 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     ai.zero();
     const bool elec_in = !SITE || r2d < rc2;
     int nlj_in = 0;
+    const double R64[3] = {dx, dy, dz};
     eval_molecule_pair<Real, C, false, TJ, SITE, ONE>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry,
-                                                      Rz, R2, ai, unused, acc, (Real)rc2, elec_in, &nlj_in);
+                                                      Rz, R2, ai, unused, acc, SiteCut{R64, &u.t.lj64[0][0][row],
+                                                      &u.t.lj64[1][0][col], rc2}, elec_in, &nlj_in);
     // interacting site pairs; in the site-site mode a listed pair counts
     // only when at least one of its site pairs interacts
     int ns = s_tab.nsite[spi][spj];

@@ -38,6 +38,7 @@ constexpr ClassShape kClassShapes[kNumClasses] = {
     {2, 2, 1, 1, 0},   // small mixed, multipoles anywhere
     {4, 4, 2, 2, 0},   // general
 };
+__host__ __device__ constexpr int class_lj(int c) { return kClassShapes[c].lj; }
 __host__ __device__ constexpr int class_reals(int c) {
   return 3 * (kClassShapes[c].lj + kClassShapes[c].ch) + 6 * (kClassShapes[c].dp + kClassShapes[c].qd);
 }
@@ -102,6 +103,7 @@ struct SlotDev {
   const double* com;          // [3][com_ld]
   const double* quat;         // [4][com_ld]
   void* sites;                // [class_reals][npad] Real
+  double* lj64;               // site-site cut-off: [3 * class LJ sites][npad] FP64 LJ-site offsets, else NULL
   void* pf;                   // [jsplits][6][npad] pair partial F, tau, in the slot's Real
   double* bsum;               // [nitems][kNumBlockSums]
   double* force;              // [3][com_ld]

@@ -1,7 +1,8 @@
 // ms2_forces without device allocation.
 //
 // The explicit pair part of one force/energy evaluation needs scratch beyond
-// the caller's inputs and outputs: the lab-frame site records, the per-tile
+// the caller's inputs and outputs: the lab-frame site records (and, in the
+// site-site cut-off mode, the FP64 LJ-site offsets), the per-tile
 // force/torque partials, the per-item block sums and the work-item list.
 // ms2_forces keeps them in context buffers that grow on the first call at a
 // larger size (that call allocates).  Here they live in one file-scope
@@ -52,13 +53,19 @@ constexpr int max_class_reals() {
   for (int c = 0; c < kNumClasses; ++c) m = class_reals(c) > m ? class_reals(c) : m;
   return m;
 }
+constexpr int max_class_lj() {
+  int m = 0;
+  for (int c = 0; c < kNumClasses; ++c) m = class_lj(c) > m ? class_lj(c) : m;
+  return m;
+}
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // byte offsets of the four regions (sized for the limit, FP64 reals)
 constexpr size_t kOffItems = 0;
 constexpr size_t kOffBsum = align256(kOffItems + (size_t)kNaItems * sizeof(WorkItem));
 constexpr size_t kOffSites = align256(kOffBsum + (size_t)kNaItems * kNumBlockSums * sizeof(double));
-constexpr size_t kOffPf = align256(kOffSites + (size_t)max_class_reals() * MS2_NOALLOC_MAX_MOL * sizeof(double));
+constexpr size_t kOffLj64 = align256(kOffSites + (size_t)max_class_reals() * MS2_NOALLOC_MAX_MOL * sizeof(double));
+constexpr size_t kOffPf = align256(kOffLj64 + (size_t)3 * max_class_lj() * MS2_NOALLOC_MAX_MOL * sizeof(double));
 constexpr size_t kScratchBytes = align256(kOffPf + (size_t)kNaTiles * 6 * MS2_NOALLOC_MAX_MOL * sizeof(double));
 static_assert(kScratchBytes <= (size_t)16 << 20, "the no-allocation scratch stays under 16 MiB");
 
@@ -155,6 +162,7 @@ extern "C" ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_param
   d.com = d_com;
   d.quat = d_quat;
   d.sites = base + kOffSites;
+  d.lj64 = h_params->cutoff_mode == MS2_CUT_SITE ? reinterpret_cast<double*>(base + kOffLj64) : nullptr;
   d.pf = base + kOffPf;
   d.pf_single = h_params->precision == MS2_FP32 ? 1 : 0;
   d.bsum = reinterpret_cast<double*>(base + kOffBsum);

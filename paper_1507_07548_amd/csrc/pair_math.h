@@ -61,6 +61,42 @@ __device__ __forceinline__ double min_image_r2(double xi, double yi, double zi, 
   return mx * mx + my * my + mz * mz;
 }
 
+// Separation of a site pair, r = R + delta, from the molecules' centre
+// difference R (components, and |R|^2 rounded once from FP64) and the
+// difference delta = d_a - d_b of the sites' lab offsets:
+//   |r|^2 = |R|^2 + (2 R.delta + delta.delta),   r.R = |R|^2 + R.delta.
+// The rounding of R's components enters only through the small terms (it
+// is scaled by |delta|), so in FP32 |r|^2 carries about one rounding of its
+// own instead of the roundings of three sums of a large and a small term
+// This holds for r comparable to R: the error of |R|^2 grows as R^2 / r^2
+// when r << R.  The pair kernels take it for the LJ sites of the model
+// classes whose sites sit close to the centre (LJ fluids, two-centre LJ +
+// quadrupole, water-like models, Stockmayer), where LJ repulsion keeps r
+// near R; charges, which approach closer, and the classes with sites far
+// off the centre take site_direct.
+template <typename Real>
+__device__ __forceinline__ void site_separation(Real Rx, Real Ry, Real Rz, Real R2, Real dx, Real dy, Real dz,
+                                                Real& rx, Real& ry, Real& rz, Real& r2, Real& rR) {
+  const Real Rd = Rx * dx + Ry * dy + Rz * dz;
+  const Real dd = dx * dx + dy * dy + dz * dz;
+  r2 = R2 + (Real(2) * Rd + dd);
+  rR = R2 + Rd;
+  rx = Rx + dx;
+  ry = Ry + dy;
+  rz = Rz + dz;
+}
+
+// The same separation formed directly: r = R + delta component by component.
+template <typename Real>
+__device__ __forceinline__ void site_direct(Real Rx, Real Ry, Real Rz, Real dx, Real dy, Real dz, Real& rx,
+                                            Real& ry, Real& rz, Real& r2, Real& rR) {
+  rx = Rx + dx;
+  ry = Ry + dy;
+  rz = Rz + dz;
+  r2 = rx * rx + ry * ry + rz * rz;
+  rR = rx * Rx + ry * Ry + rz * Rz;
+}
+
 // ---------------------------------------------------------------------------
 // Orientation-dependent Coulomb terms of point multipoles.
 // u = K * P(ca, cb, cab) * r^-p with ca = ea.n, cb = eb.n, cab = ea.eb and n
@@ -155,6 +191,9 @@ __device__ __forceinline__ void mp_site_pair(Real K, const Real* pa, const Real*
   constexpr int p = MpPower<TA, TB>::p;
   // the class guarantees centred dipoles/quadrupoles, not centred charges
   constexpr bool CENTRAL = CENTRAL_CLASS && TA != 1 && TB != 1;
+  // off-centre multipoles may approach much closer than their centres
+  // (r << R), where the expansion of site_separation loses what it gains
+  // elsewhere: r is formed directly
   Real rx = Rx, ry = Ry, rz = Rz, r2 = R2;
   if constexpr (!CENTRAL) {
     rx += pa[0] - pb[0];
@@ -276,7 +315,10 @@ struct PairTables {
   Real c6[MAXSP * NLJ][MAXSP * NLJ];
   Real c12[MAXSP * NLJ][MAXSP * NLJ];
   int cnt[MAXSP][4];
-  Real mch[MAXSP][NCH], mdp[MAXSP][NDP], mqd[MAXSP][NQD];   // k_e * magnitude
+  // k_e * magnitude, in FP64: the prefactor k_e m_a m_b of an electrostatic
+  // site pair is formed in FP64 and rounded to Real once (kprod), so that
+  // every pair of a kind carries the same single rounding of it at most
+  double mch[MAXSP][NCH], mdp[MAXSP][NDP], mqd[MAXSP][NQD];
   int nsite[MAXSP][MAXSP];
 
   // nsp: the species in use (1 when every molecule is species 0, whatever
@@ -297,9 +339,9 @@ struct PairTables {
     for (int e = tid; e < nsp; e += nthreads) {
       const SpeciesDev& D = tab->sp[e];
       cnt[e][0] = D.nlj; cnt[e][1] = D.nch; cnt[e][2] = D.ndp; cnt[e][3] = D.nqd;
-      for (int a = 0; a < NCH; ++a) mch[e][a] = (Real)(P.ke * D.ch_q[a]);
-      for (int a = 0; a < NDP; ++a) mdp[e][a] = (Real)(P.ke * D.dp_mu[a]);
-      for (int a = 0; a < NQD; ++a) mqd[e][a] = (Real)(P.ke * D.qd_Q[a]);
+      for (int a = 0; a < NCH; ++a) mch[e][a] = P.ke * D.ch_q[a];
+      for (int a = 0; a < NDP; ++a) mdp[e][a] = P.ke * D.dp_mu[a];
+      for (int a = 0; a < NQD; ++a) mqd[e][a] = P.ke * D.qd_Q[a];
       for (int b = 0; b < nsp; ++b) nsite[e][b] = tab->nsite_pair[e][b];
     }
   }
@@ -309,11 +351,42 @@ struct PairTables {
 template <typename Real>
 struct ElecParams {
   int elec;
-  Real krf, crf, alpha, alpha2, gpref, inv_ke;
+  Real krf, crf, alpha, alpha2, gpref;
+  double inv_ke;
+};
+
+// k_e m_a m_b from the FP64 magnitudes (each k_e m), rounded once.
+template <typename Real>
+__device__ __forceinline__ Real kprod(double ma, double mb, double inv_ke) {
+  return (Real)(ma * mb * inv_ke);
+}
+
+// The FP64 decision of the site-site cut-off for LJ site pair (a, b):
+// r = (R + d_a) - d_b from the FP64 minimum-image centre difference R and
+// the FP64 lab offsets of the two sites (component k of site a at
+// li[3 a + k] times the stride), |r|^2 summed in the order x, y, z, each
+// operation rounded as written, accepted iff |r|^2 < rc^2 -- the same
+// arithmetic, so the same decision, as a plain FP64 evaluation.
+struct SiteCut {
+  const double* R = nullptr;    // [3]
+  const double* li = nullptr;   // LJ offsets of molecule i
+  const double* lj = nullptr;   // LJ offsets of molecule j
+  double rc2 = 0.0;
+  __device__ __forceinline__ bool inside(int a, int b, int stride) const {
+#pragma clang fp contract(off)
+    const double x = (R[0] + li[(3 * a) * stride]) - lj[(3 * b) * stride];
+    const double y = (R[1] + li[(3 * a + 1) * stride]) - lj[(3 * b + 1) * stride];
+    const double z = (R[2] + li[(3 * a + 2) * stride]) - lj[(3 * b + 2) * stride];
+    double r2 = x * x;
+    r2 = r2 + y * y;
+    r2 = r2 + z * z;
+    return r2 < rc2;
+  }
 };
 
 // All site pairs of one accepted molecule pair (i, j) with centre difference
-// R = R_i - R_j.  rec: the site record of i (registers); sj: the record of j,
+// R = R_i - R_j (components Rx, Ry, Rz and R2 = |R|^2, each rounded once
+// from the FP64 minimum-image difference).  rec: the site record of i (registers); sj: the record of j,
 // component k at sj[k * STRIDE] (LDS).  Forces and orientation gradients on
 // i's sites go to ai; with JSIDE those on j's sites go to aj (force on a j
 // site is minus the force on its partner).  acc collects the pair's energy,
@@ -321,16 +394,17 @@ struct ElecParams {
 // ONE: the system has one species (spi = spj = 0); its site counts are then
 // wave-uniform and the site loops branch on scalars.
 // SITE: the site-site cut-off mode.  An LJ site pair then interacts only
-// when its own squared distance is below lj_rc2 (and adds one to *nlj_in),
-// and the electrostatic site pairs only when elec_in (the centres inside the
-// cut-off).  Without SITE every site pair of the molecule pair interacts.
+// when its own squared distance is below rc^2, decided in FP64 by `cut`
+// (and adds one to *nlj_in), and the electrostatic site pairs only when
+// elec_in (the centres inside the cut-off).  Without SITE every site pair of
+// the molecule pair interacts.
 template <typename Real, int C, bool JSIDE, int STRIDE, bool SITE = false, bool ONE = false>
 __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* sj, int spi, int spj,
                                                    const PairTables<Real, C, ONE ? 1 : kMaxSp>& T,
                                                    const ElecParams<Real>& E, Real Rx, Real Ry,
                                                    Real Rz, Real R2, SiteAcc<Real, C>& ai,
                                                    SiteAcc<Real, C>& aj, PairAcc<Real>& acc,
-                                                   Real lj_rc2 = Real(0), bool elec_in = true,
+                                                   SiteCut cut = SiteCut{}, bool elec_in = true,
                                                    int* nlj_in = nullptr) {
   constexpr ClassShape S = kClassShapes[C];
   constexpr int NLJ = SiteAcc<Real, C>::NLJ;
@@ -359,23 +433,26 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
 #pragma unroll
     for (int b = 0; b < S.lj; ++b) {
       if (b >= nlj_j) break;
-      const Real rx = Rx + rec[3 * a] - J(3 * b);
-      const Real ry = Ry + rec[3 * a + 1] - J(3 * b + 1);
-      const Real rz = Rz + rec[3 * a + 2] - J(3 * b + 2);
-      const Real r2 = rx * rx + ry * ry + rz * rz;
+      Real rx, ry, rz, r2, rR;
+      if constexpr (CENTRAL) {
+        site_separation(Rx, Ry, Rz, R2, rec[3 * a] - J(3 * b), rec[3 * a + 1] - J(3 * b + 1),
+                        rec[3 * a + 2] - J(3 * b + 2), rx, ry, rz, r2, rR);
+      } else {
+        site_direct(Rx, Ry, Rz, rec[3 * a] - J(3 * b), rec[3 * a + 1] - J(3 * b + 1),
+                    rec[3 * a + 2] - J(3 * b + 2), rx, ry, rz, r2, rR);
+      }
       const Real ir2 = rcp_(r2);
       const Real ir6 = ir2 * ir2 * ir2;
       Real t6 = T.c6[spi * NLJ + a][spj * NLJ + b] * ir6;
       Real t12 = T.c12[spi * NLJ + a][spj * NLJ + b] * ir6 * ir6;
       if constexpr (SITE) {
-        const bool in = r2 < lj_rc2;
+        const bool in = cut.inside(a, b, STRIDE);
         *nlj_in += in ? 1 : 0;
         t6 = in ? t6 : Real(0);
         t12 = in ? t12 : Real(0);
       }
       const Real dur = (Real(6) * t6 - Real(12) * t12) * ir2;       // u'/r
       const Real d2u = (Real(156) * t12 - Real(42) * t6) * ir2;     // u''
-      const Real rR = rx * Rx + ry * Ry + rz * Rz;
       acc.ulj += t12 - t6;
       acc.uss += (d2u - dur) * (rR * rR * ir2) + dur * R2;
       const Real fx = -dur * rx, fy = -dur * ry, fz = -dur * rz;
@@ -393,11 +470,11 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
 #pragma unroll
       for (int b = 0; b < S.ch; ++b) {
         if (b >= nch_j) break;
-        const Real K = T.mch[spi][a] * T.mch[spj][b] * E.inv_ke;
-        const Real rx = Rx + rec[OFF_CH + 3 * a] - J(OFF_CH + 3 * b);
-        const Real ry = Ry + rec[OFF_CH + 3 * a + 1] - J(OFF_CH + 3 * b + 1);
-        const Real rz = Rz + rec[OFF_CH + 3 * a + 2] - J(OFF_CH + 3 * b + 2);
-        const Real r2 = rx * rx + ry * ry + rz * rz;
+        const Real K = kprod<Real>(T.mch[spi][a], T.mch[spj][b], E.inv_ke);
+        Real rx, ry, rz, r2, rR;
+        site_direct(Rx, Ry, Rz, rec[OFF_CH + 3 * a] - J(OFF_CH + 3 * b),
+                    rec[OFF_CH + 3 * a + 1] - J(OFF_CH + 3 * b + 1),
+                    rec[OFF_CH + 3 * a + 2] - J(OFF_CH + 3 * b + 2), rx, ry, rz, r2, rR);
         const Real ir = rsq_(r2), ir2 = ir * ir;
         Real u, dur, d2u;
         if (E.elec == MS2_ELEC_EWALD) {
@@ -416,7 +493,6 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
           dur = -K * ir * ir2;
           d2u = Real(2) * K * ir * ir2;
         }
-        const Real rR = rx * Rx + ry * Ry + rz * Rz;
         acc.uel += u;
         acc.uss += (d2u - dur) * (rR * rR * ir2) + dur * R2;
         const Real fx = -dur * rx, fy = -dur * ry, fz = -dur * rz;
@@ -455,7 +531,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
             Real pb[3], eb[3];
             jrec(OFF_DP + 6 * b, pb);
             jrec(OFF_DP + 6 * b + 3, eb);
-            pair(SitePairTag<1, 2>{}, T.mch[spi][a] * T.mdp[spj][b] * E.inv_ke, pa, zero3, pb, eb, ai.fc[a], gdummy,
+            pair(SitePairTag<1, 2>{}, kprod<Real>(T.mch[spi][a], T.mdp[spj][b], E.inv_ke), pa, zero3, pb, eb, ai.fc[a], gdummy,
                  aj.fd[b], aj.gd[b]);
           }
         }
@@ -466,7 +542,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
             Real pb[3], eb[3];
             jrec(OFF_QD + 6 * b, pb);
             jrec(OFF_QD + 6 * b + 3, eb);
-            pair(SitePairTag<1, 3>{}, T.mch[spi][a] * T.mqd[spj][b] * E.inv_ke, pa, zero3, pb, eb, ai.fc[a], gdummy,
+            pair(SitePairTag<1, 3>{}, kprod<Real>(T.mch[spi][a], T.mqd[spj][b], E.inv_ke), pa, zero3, pb, eb, ai.fc[a], gdummy,
                  aj.fq[b], aj.gq[b]);
           }
         }
@@ -484,7 +560,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
             if (b >= nch_j) break;
             Real pb[3];
             jrec(OFF_CH + 3 * b, pb);
-            pair(SitePairTag<2, 1>{}, T.mdp[spi][a] * T.mch[spj][b] * E.inv_ke, pa, ea, pb, zero3, ai.fd[a], ai.gd[a],
+            pair(SitePairTag<2, 1>{}, kprod<Real>(T.mdp[spi][a], T.mch[spj][b], E.inv_ke), pa, ea, pb, zero3, ai.fd[a], ai.gd[a],
                  aj.fc[b], gdummy);
           }
         }
@@ -494,7 +570,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
           Real pb[3], eb[3];
           jrec(OFF_DP + 6 * b, pb);
           jrec(OFF_DP + 6 * b + 3, eb);
-          pair(SitePairTag<2, 2>{}, T.mdp[spi][a] * T.mdp[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fd[a], ai.gd[a],
+          pair(SitePairTag<2, 2>{}, kprod<Real>(T.mdp[spi][a], T.mdp[spj][b], E.inv_ke), pa, ea, pb, eb, ai.fd[a], ai.gd[a],
                aj.fd[b], aj.gd[b]);
         }
         if constexpr (S.qd > 0) {
@@ -504,7 +580,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
             Real pb[3], eb[3];
             jrec(OFF_QD + 6 * b, pb);
             jrec(OFF_QD + 6 * b + 3, eb);
-            pair(SitePairTag<2, 3>{}, T.mdp[spi][a] * T.mqd[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fd[a], ai.gd[a],
+            pair(SitePairTag<2, 3>{}, kprod<Real>(T.mdp[spi][a], T.mqd[spj][b], E.inv_ke), pa, ea, pb, eb, ai.fd[a], ai.gd[a],
                  aj.fq[b], aj.gq[b]);
           }
         }
@@ -522,7 +598,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
             if (b >= nch_j) break;
             Real pb[3];
             jrec(OFF_CH + 3 * b, pb);
-            pair(SitePairTag<3, 1>{}, T.mqd[spi][a] * T.mch[spj][b] * E.inv_ke, pa, ea, pb, zero3, ai.fq[a], ai.gq[a],
+            pair(SitePairTag<3, 1>{}, kprod<Real>(T.mqd[spi][a], T.mch[spj][b], E.inv_ke), pa, ea, pb, zero3, ai.fq[a], ai.gq[a],
                  aj.fc[b], gdummy);
           }
         }
@@ -533,7 +609,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
             Real pb[3], eb[3];
             jrec(OFF_DP + 6 * b, pb);
             jrec(OFF_DP + 6 * b + 3, eb);
-            pair(SitePairTag<3, 2>{}, T.mqd[spi][a] * T.mdp[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fq[a], ai.gq[a],
+            pair(SitePairTag<3, 2>{}, kprod<Real>(T.mqd[spi][a], T.mdp[spj][b], E.inv_ke), pa, ea, pb, eb, ai.fq[a], ai.gq[a],
                  aj.fd[b], aj.gd[b]);
           }
         }
@@ -543,7 +619,7 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
           Real pb[3], eb[3];
           jrec(OFF_QD + 6 * b, pb);
           jrec(OFF_QD + 6 * b + 3, eb);
-          pair(SitePairTag<3, 3>{}, T.mqd[spi][a] * T.mqd[spj][b] * E.inv_ke, pa, ea, pb, eb, ai.fq[a], ai.gq[a],
+          pair(SitePairTag<3, 3>{}, kprod<Real>(T.mqd[spi][a], T.mqd[spj][b], E.inv_ke), pa, ea, pb, eb, ai.fq[a], ai.gq[a],
                aj.fq[b], aj.gq[b]);
         }
       }

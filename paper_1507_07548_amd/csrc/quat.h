@@ -6,7 +6,11 @@
 
 namespace ms2 {
 
+// Rounded exactly as written (no contraction into fused multiply-adds), so
+// that site offsets built from it equal a plain FP64 evaluation of the same
+// expressions bit for bit (the site-site cut-off decides on them).
 __device__ __forceinline__ void quat_matrix(double w, double x, double y, double z, double A[3][3]) {
+#pragma clang fp contract(off)
   A[0][0] = 1.0 - 2.0 * (y * y + z * z);
   A[0][1] = 2.0 * (x * y - w * z);
   A[0][2] = 2.0 * (x * z + w * y);

@@ -10,6 +10,10 @@
   select <results.db> <substring;substring;...>
       per kernel and grid size, calls and durations of the kernels whose
       name holds one of the ';'-separated substrings.
+  gaps <results.db> <marker substring> <steps>
+      device idle time between kernels over the last <steps> steps of a
+      run: a step starts at a dispatch of the marker kernel (one per step);
+      prints per step the span, the kernels' busy time and the idle rest.
   traffic <fetch.csv> <write.csv> <copy_bytes> <kernel substring>
       HBM bytes per launch of the largest-grid dispatches whose name holds
       the substring, from two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
@@ -72,6 +76,43 @@ def select(db_path, substrings):
         if any(sub in name for sub in substrings):
             out.append(f"| `{name.split('(')[0]}` | {grid} | {calls} | {avg / 1e3:.1f} | {tot / 1e6:.2f} |")
     return "\n".join(out)
+
+
+def _kernel_intervals(con):
+    cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
+    for a, b in (("start", "end"), ("start_ns", "end_ns"), ("begin", "end")):
+        if a in cols and b in cols:
+            return con.execute(f'select name, "{a}", "{b}" from kernels order by "{a}"').fetchall()
+    raise SystemExit(f"kernels table without start/end columns: {cols}")
+
+
+def gaps(db_path, marker, steps):
+    """Per step over the last `steps` steps: span (first marker dispatch of a
+    step to the next one's), summed kernel time inside it (overlaps merged)
+    and the idle rest, in microseconds."""
+    con = sqlite3.connect(db_path)
+    rows = _kernel_intervals(con)
+    starts = [a for n, a, _ in rows if marker in n]
+    if len(starts) < steps + 1:
+        raise SystemExit(f"fewer than {steps + 1} dispatches of {marker!r}")
+    t0, t1 = starts[-steps - 1], starts[-1]
+    busy, cur_a, cur_b = 0, None, None
+    for _, a, b in rows:
+        a, b = max(a, t0), min(b, t1)
+        if b <= a:
+            continue
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                busy += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    if cur_b is not None:
+        busy += cur_b - cur_a
+    per = [(t1 - t0) / steps / 1e3, busy / steps / 1e3]
+    n_k = sum(1 for _, a, b in rows if a >= t0 and a < t1)
+    return {"span_us": per[0], "busy_us": per[1], "idle_us": per[0] - per[1],
+            "idle_frac": 1.0 - per[1] / per[0], "kernels_per_step": n_k / steps}
 
 
 def _dispatches(csv_path, counter):
@@ -148,6 +189,11 @@ if __name__ == "__main__":
         print(counters(sys.argv[2], sys.argv[3]))
     elif len(sys.argv) >= 2 and sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5]))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "gaps":
+        g = gaps(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+        print(f"per step over the last {sys.argv[4]} steps: span {g['span_us']:.1f} us, kernels busy "
+              f"{g['busy_us']:.1f} us, idle {g['idle_us']:.1f} us ({100 * g['idle_frac']:.1f} %), "
+              f"{g['kernels_per_step']:.1f} kernels per step")
     elif len(sys.argv) >= 2 and sys.argv[1] == "select":
         print(select(sys.argv[2], sys.argv[3].split(";")))
     elif len(sys.argv) >= 2 and sys.argv[1] == "kernels":

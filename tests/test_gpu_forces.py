@@ -329,7 +329,10 @@ def test_symmetric_tiles_on_every_site_type(n, elec):
         ctx.set_tile_config(s.n, prec, 0, 64, mode=0)
         f, t, su, fo, to, so, ef, et = compare(s, prec, ctx=ctx, label=f"symmetric offset elec={elec}")
         assert ef < tol and et < tol, (ef, et)
-        check_sums(su, so, 1e-11 if prec == ms2.FP64 else 1e-6, 1e-12 if prec == ms2.FP64 else 1e-8)
+        # FP32: these random starts overlap sites (the virial, ~100, is a small
+        # remainder of terms summing to ~7e3 in magnitude), so the sums are
+        # held to 5e-8 of the summed magnitudes besides 1e-6 of themselves
+        check_sums(su, so, 1e-11 if prec == ms2.FP64 else 1e-6, 1e-12 if prec == ms2.FP64 else 5e-8)
 
 
 def test_symmetric_tiles_ewald_water_ions():

@@ -4,8 +4,8 @@ field and partial enthalpies (Gear, dipoles), and one-site LJ (velocity
 Verlet).  FP64 trajectories agree to ~1e-12 and the flux is a sum of terms of
 both signs, so the ACF sums agree to ~1e-9 relative to their first lag (the
 tolerance below).  The FP32 form: pair terms carry ~1e-7 relative error each,
-summed over ~1e5 pairs with cancellation; the first lag within 1e-3.  And
-alone = in a mix, bitwise."""
+summed over ~1e5 pairs with cancellation; every lag within 1e-4 of the
+first.  And alone = in a mix, bitwise."""
 import numpy as np
 import pytest
 
@@ -69,14 +69,23 @@ def test_heat_flux_acf_matches_the_oracle_fp64(name):
     np.testing.assert_allclose(g["acf_q"], o["acf_q"], rtol=0, atol=1e-9 * o["acf_q"][0])
 
 
-def test_heat_flux_acf_fp32_tracks_fp64():
-    s = systems()["2cljq_gear"]
-    s.md.n_steps = 6
-    say("[gpu] heat-flux ACF, 2CLJQ, fp32 vs fp64 oracle, 6 steps")
+@pytest.mark.parametrize("name", ["2cljq_gear", "stockmayer_rf_gear", "lj_vv"])
+def test_heat_flux_acf_fp32_every_lag(name):
+    """FP32 site arithmetic against the FP64 oracle at every lag of the 30-step
+    run.  J_q's pair part (Sec. 5, Eq. 6) is a sum of terms of both signs
+    whose magnitudes exceed the sum by C ~ 1e2; each FP32 term carries a
+    few 1e-7 of itself, so J_q is good to ~1e-5 relative, an ACF value (a
+    product of two fluxes averaged over origins) to twice that, and the
+    trajectory itself, integrated with FP32 forces, departs from the FP64
+    one by ~1e-6 over 30 steps: every lag within 1e-4 of acf(0)."""
+    s = systems()[name]
+    say(f"[gpu] heat-flux ACF, {name}, fp32 vs fp64 oracle, {s.md.n_steps} steps")
     o = oracle.md(s, want_log=False)
     g = run(s, ms2.FP32)
     np.testing.assert_array_equal(g["acf_q_cnt"], o["acf_q_cnt"])
-    assert g["acf_q"][0] == pytest.approx(o["acf_q"][0], rel=1e-3)
+    err = np.abs(g["acf_q"] - o["acf_q"]) / o["acf_q"][0]
+    say(f"  max over lags |d acf| / acf(0) {err.max():.2e}; per lag {np.array2string(err, precision=1)}")
+    assert err.max() < 1e-4
 
 
 def test_heat_flux_alone_and_in_a_mix_are_identical():

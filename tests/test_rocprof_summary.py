@@ -74,11 +74,10 @@ def test_traffic_scales_each_counter_by_the_copy(tmp_path, monkeypatch):
     assert "- hbm_bytes_per_launch: 4.608e+06" in text
     summary = tmp_path / "summary.md"
     summary.write_text("# traffic\n\n" + text + "\n")
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
-    assert bench.recorded_traffic() == pytest.approx(4.608e6)
+    assert bench.recorded(str(summary), "hbm_bytes_per_launch") == pytest.approx(4.608e6)
     # a change of the pair kernel sources voids the record
     monkeypatch.setattr(R, "pair_kernel_source_hash", lambda: "0" * 64)
-    assert bench.recorded_traffic() is None
+    assert bench.recorded(str(summary), "hbm_bytes_per_launch") is None
     with pytest.raises(SystemExit):          # no copy of known size in the run
         R.traffic(counter_csv(str(tmp_path / "g.csv"), "FETCH_SIZE", [(2, SYM, 1000, 1.0)]), write, gib,
                   "pair_sym_kernel<float")
@@ -99,3 +98,25 @@ def test_source_hash_follows_every_pair_kernel_file(tmp_path, monkeypatch):
         assert R.pair_kernel_source_hash() != base, rel
         f.write_bytes(orig)
     assert R.pair_kernel_source_hash() == base
+
+
+def test_gaps_per_step_over_the_last_steps(tmp_path):
+    """Three kernels per step with 5 us gaps: over the last three steps, span
+    145 us, busy 130 us; a kernel overlapping another (another stream) is
+    counted once; the steps before the window are left out."""
+    con = sqlite3.connect(str(tmp_path / "g.db"))
+    con.execute('create table kernels (name text, start int, "end" int)')
+    t, rows = 0, []
+    for step in range(5):
+        for name, dur in ((SYM, 100_000), ("ms2::reduce_force_kernel", 20_000), ("ms2::md_end", 10_000)):
+            rows.append((name, t, t + dur))
+            t += dur + 5_000
+    rows.append(("overlap", rows[6][1] + 1_000, rows[6][1] + 50_000))    # inside step 2's pair kernel
+    con.executemany("insert into kernels values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    g = R.gaps(str(tmp_path / "g.db"), "pair_sym_kernel", 3)
+    assert g["span_us"] == pytest.approx(145.0) and g["busy_us"] == pytest.approx(130.0)
+    assert g["idle_frac"] == pytest.approx(15.0 / 145.0)
+    with pytest.raises(SystemExit):
+        R.gaps(str(tmp_path / "g.db"), "pair_sym_kernel", 5)
