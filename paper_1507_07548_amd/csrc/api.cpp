@@ -20,7 +20,7 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, int form,
                        const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
@@ -328,12 +328,36 @@ TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
   return c;
 }
 
-bool single_species_form(const ms2_ctx* ctx) {
+static bool single_species_form(const ms2_ctx* ctx) {
   if (ctx->tab.nsp != 1) return false;
   const SpeciesDev& d = ctx->tab.sp[0];
   const ClassShape& S = kClassShapes[ctx->cls];
   return (S.lj == 0 || d.nlj >= 1) && (S.ch == 0 || d.nch >= 1) && (S.dp == 0 || d.ndp >= 1) &&
          (S.qd == 0 || d.nqd >= 1);
+}
+
+double linear_h(const ms2_ctx* ctx) {
+  if (ctx->cls != 1 || !single_species_form(ctx)) return 0.0;
+  const SpeciesDev& d = ctx->tab.sp[0];
+  if (d.nlj != 2 || d.nqd != 1 || d.nch != 0 || d.ndp != 0) return 0.0;
+  const double* a = d.lj_pos[0];
+  const double* b = d.lj_pos[1];
+  const double* e = d.qd_axis[0];
+  const double* q = d.qd_pos[0];
+  if (q[0] != 0.0 || q[1] != 0.0 || q[2] != 0.0) return 0.0;
+  if (d.lj_sigma[0] != d.lj_sigma[1] || d.lj_eps[0] != d.lj_eps[1]) return 0.0;
+  if (a[0] != -b[0] || a[1] != -b[1] || a[2] != -b[2]) return 0.0;   // symmetric about the centre
+  const double h = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  if (!(h > 0.0)) return 0.0;
+  // on the axis: a = +-h e to rounding
+  const double cx = a[1] * e[2] - a[2] * e[1], cy = a[2] * e[0] - a[0] * e[2], cz = a[0] * e[1] - a[1] * e[0];
+  if (std::sqrt(cx * cx + cy * cy + cz * cz) > 1e-12 * h) return 0.0;
+  return h;
+}
+
+int pair_form(const ms2_ctx* ctx) {
+  if (linear_h(ctx) > 0.0) return kFormLinear;
+  return single_species_form(ctx) ? kFormOneSpecies : kFormGeneral;
 }
 
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits) {
@@ -578,7 +602,7 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
   const ms2::CachedItems& ci = ctx->item_cache[std::make_tuple(n_mol, cfg.waves, cfg.jchunk)];
   MS2_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n_mol, st));
   MS2_HIP(launch_pair(ctx->cls, h_params->precision, cfg.waves, false, h_params->cutoff_mode == MS2_CUT_SITE,
-                      single_species_form(ctx), (const WorkItem*)ci.buf.p, 0, nitems,
+                      pair_form(ctx), (const WorkItem*)ci.buf.p, 0, nitems,
                       r->d_slot, r->d_prm, ctx->d_tab, st));
   MS2_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, n_mol, st));
   MS2_HIP(hipEventRecord(r->ev, st));

@@ -21,9 +21,7 @@
 #include "batch.h"
 
 namespace ms2 {
-hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
-                             const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, int form,
                        const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
@@ -34,8 +32,8 @@ hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const Speci
 hipError_t launch_md_wrap(MDDev* md, const SysParams* prm, int slot, int n, hipStream_t st);
 hipError_t launch_md_init(SlotDev* slots, MDDev* md, const SpeciesTable* tab, int slot,
                           hipStream_t st);
-hipError_t launch_md_begin(const SlotDev* slots, MDDev* md, const SysParams* prm,
-                           const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
+hipError_t launch_md_begin_frame(int cls, int precision, const SlotDev* slots, MDDev* md, const SysParams* prm,
+                                 const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
 hipError_t launch_residence(const SlotDev* slots, MDDev* md, const SysParams* prm, int slot_base,
                             int nslots, int max_solute, hipStream_t st);
 hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const SpeciesTable* tab,
@@ -350,20 +348,16 @@ void rebuild_items(ms2_batch* b) {
   b->dirty = false;
 }
 
-// the force path for every slot of the batch (pair part + reduction + k-space)
+// the force path for every slot of the batch after the site frame (pair
+// part + reduction + k-space)
 ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
   ms2_ctx* ctx = b->ctx;
   const SlotDev* ds = (const SlotDev*)b->d_slots.p;
   const SysParams* dp = (const SysParams*)b->d_prm.p;
   const WorkItem* di = (const WorkItem*)b->d_items.p;
-  for (int prec : {MS2_FP64, MS2_FP32}) {
-    bool any = false;
-    for (auto& g : b->groups) any |= g.precision == prec;
-    if (any) MS2_HIP(launch_site_frame(ctx->cls, prec, ds, dp, ctx->d_tab, b->max_slots, b->max_n, st));
-  }
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_begin[timed_step], st));
   for (auto& g : b->groups)
-    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, single_species_form(ctx), di, g.begin,
+    MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, pair_form(ctx), di, g.begin,
                         g.end - g.begin, ds, dp, ctx->d_tab, st));
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
   MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
@@ -378,7 +372,12 @@ ms2_status enqueue_step(ms2_batch* b, hipStream_t st, int timed_step) {
   SlotDev* ds = (SlotDev*)b->d_slots.p;
   MDDev* dm = (MDDev*)b->d_md.p;
   const SysParams* dp = (const SysParams*)b->d_prm.p;
-  MS2_HIP(launch_md_begin(ds, dm, dp, ctx->d_tab, b->max_slots, b->max_n, st));
+  // predictor and site frame, one launch per precision in use
+  for (int prec : {MS2_FP64, MS2_FP32}) {
+    bool any = false;
+    for (auto& g : b->groups) any |= g.precision == prec;
+    if (any) MS2_HIP(launch_md_begin_frame(ctx->cls, prec, ds, dm, dp, ctx->d_tab, b->max_slots, b->max_n, st));
+  }
   ms2_status s = enqueue_forces(b, st, timed_step);
   if (s != MS2_OK) return s;
   MS2_HIP(launch_md_end(ds, dm, dp, ctx->d_tab, b->max_slots, b->max_n, st));

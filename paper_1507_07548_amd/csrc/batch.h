@@ -68,9 +68,14 @@ ms2_status kvec_table(ms2_ctx* ctx, int kmax2, const KVec** d_out, int* nk);
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n);
 int size_bucket(int n);
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits);
-// true when the pair kernels may take their single-species form: one species,
-// with at least one site of every kind its model class holds
-bool single_species_form(const ms2_ctx* ctx);
+// the form of the symmetric pair kernel a context takes (PairForm): the
+// single-species form needs one species with at least one site of every
+// kind its model class holds; the linear form in addition a two-centre LJ +
+// quadrupole molecule with both LJ sites (equal parameters) at +-h on the
+// quadrupole's axis and the quadrupole at the centre
+int pair_form(const ms2_ctx* ctx);
+// h of the linear form, or 0 when the context's species is not of that shape
+double linear_h(const ms2_ctx* ctx);
 int kvec_count(int kmax2);
 // next block of the context's ring of pinned parameter blocks (waits for
 // the call that used it last)

@@ -25,78 +25,23 @@
 #include "internal.h"
 #include "pair_math.h"
 #include "quat.h"
+#include "site_frame.h"
 
 namespace ms2 {
 
-// One component of A b, rounded exactly as written (no fused multiply-add):
-// equal bit for bit to a plain FP64 evaluation of the same sum.
-__device__ __forceinline__ double rotate_row(const double* a, const double* b) {
-#pragma clang fp contract(off)
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
-
 // ---------------------------------------------------------------------------
-// Site frame: d = A(q) b and e = A(q) ehat for every site of every molecule.
-// Record layout per class: [lj 3*NLJ][ch 3*NCH][dp 6*NDP][qd 6*NQD], each
-// real stored as a row of length npad (structure of arrays).
+// Site frame of every molecule of every slot of this precision.
 // ---------------------------------------------------------------------------
 template <typename Real, int C>
 __global__ __launch_bounds__(256) void site_frame_kernel(const SlotDev* __restrict__ slots,
                                                          const SysParams* __restrict__ prm,
                                                          const SpeciesTable* __restrict__ tab) {
-  constexpr ClassShape S = kClassShapes[C];
   const SlotDev& sd = slots[blockIdx.y];
   if (!sd.active) return;
   if (prm[blockIdx.y].precision != (sizeof(Real) == 4 ? MS2_FP32 : MS2_FP64)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= sd.n) return;
-  const int ld = sd.com_ld, np = sd.npad;
-  Real* out = reinterpret_cast<Real*>(sd.sites);
-  const SpeciesDev& D = tab->sp[clamp_species(sd.species[i], tab->nsp)];
-  double A[3][3];
-  quat_matrix(sd.quat[i], sd.quat[ld + i], sd.quat[2 * ld + i], sd.quat[3 * ld + i], A);
-  int k = 0;
-  auto put = [&](const double* b, int valid) {
-    for (int c = 0; c < 3; ++c) {
-      double v = valid ? rotate_row(A[c], b) : 0.0;
-      out[(k + c) * np + i] = (Real)v;
-    }
-    k += 3;
-  };
-#pragma unroll
-  for (int a = 0; a < S.lj; ++a) put(D.lj_pos[a < D.nlj ? a : 0], a < D.nlj);
-  if (sd.lj64) {
-    // site-site cut-off: the LJ-site offsets in FP64 as well, for the
-    // decision r_ab^2 < rc^2 (taken in FP64 whatever the pair precision)
-#pragma unroll
-    for (int a = 0; a < S.lj; ++a)
-      for (int c = 0; c < 3; ++c)
-        sd.lj64[(3 * a + c) * np + i] = a < D.nlj ? rotate_row(A[c], D.lj_pos[a]) : 0.0;
-  }
-#pragma unroll
-  for (int a = 0; a < S.ch; ++a) put(D.ch_pos[a < D.nch ? a : 0], a < D.nch);
-#pragma unroll
-  for (int a = 0; a < S.dp; ++a) {
-    put(D.dp_pos[a < D.ndp ? a : 0], a < D.ndp);
-    put(D.dp_axis[a < D.ndp ? a : 0], a < D.ndp);
-  }
-#pragma unroll
-  for (int a = 0; a < S.qd; ++a) {
-    put(D.qd_pos[a < D.nqd ? a : 0], a < D.nqd);
-    put(D.qd_axis[a < D.nqd ? a : 0], a < D.nqd);
-  }
-  if (sd.hf_kin) {
-    // lab-frame velocity and angular velocity of the state the forces are
-    // evaluated at (heat flux)
-    Real* kin = reinterpret_cast<Real*>(sd.hf_kin);
-    double wb[3] = {0.0, 0.0, 0.0};
-    if (sd.hf_w)
-      for (int c = 0; c < 3; ++c) wb[c] = sd.hf_w[c * ld + i];
-    for (int c = 0; c < 3; ++c) {
-      kin[c * np + i] = (Real)(sd.hf_v[c * ld + i] * sd.hf_vscale);
-      kin[(3 + c) * np + i] = (Real)(A[c][0] * wb[0] + A[c][1] * wb[1] + A[c][2] * wb[2]);
-    }
-  }
+  site_frame_molecule<Real, C>(sd, tab, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,7 +317,7 @@ struct SymFinal {
 // two-centre quadrupole kernel of the centre cut-off (it fits 80 registers
 // without spilling, and the kernel hides its LDS latency better with six
 // waves than with five); the compiler's choice otherwise.
-template <typename Real, int C, bool HF, bool SITE>
+template <typename Real, int C, bool HF, bool SITE, bool LIN>
 constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6
                               : (sizeof(Real) == 8 && C == 1 && !HF && !SITE) ? 4
                                                                              : 1;
@@ -381,14 +326,24 @@ constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6
 // one site of every kind its class holds (instantiated for classes 0-3); the
 // species reads and table indexing drop out, and the first site pair of each
 // kind starts its sums.
-template <typename Real, int C, bool HF, bool SITE, bool ONE>
-__global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(kSymOccupancy<Real, C, HF, SITE>)))
+// LIN (class 1, ONE, centre cut-off, no heat flux, FP32): the species is a
+// linear two-centre LJ + quadrupole molecule (eval_linear_pair); only the
+// first LJ site's offset and the quadrupole axis of each molecule are staged
+// (278 instead of 319 VALU instructions in the pair loop; 4.37 -> 4.29 ms on
+// the batched 2CLJQ workload).
+template <typename Real, int C, bool HF, bool SITE, bool ONE, bool LIN = false>
+__global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(kSymOccupancy<Real, C, HF, SITE, LIN>)))
 void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   int item_base,
                                                                   const SlotDev* __restrict__ slots,
                                                                   const SysParams* __restrict__ prm,
                                                                   const SpeciesTable* __restrict__ tab) {
-  constexpr int NR = class_reals(C);
+  static_assert(!LIN || (C == 1 && ONE && !HF && !SITE && sizeof(Real) == 4),
+                "the linear form is a class-1 single-species FP32 form");
+  // reals of the site record staged per molecule: all of them, or (LIN) the
+  // first LJ site's offset (the record's first three) and the quadrupole
+  // axis (its last three)
+  constexpr int NR = LIN ? 6 : class_reals(C);
   constexpr int TJ = 64, NW = kSymWaves;
 
   constexpr int NL64 = SITE ? 3 * kClassShapes[C].lj : 0;
@@ -419,6 +374,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   // within the radius at which an LJ site pair can still reach
   const double rlist2 = SITE ? P.rc2_search : rc2;
   const ElecParams<Real> E = elec_params<Real>(P);
+  LinearModel<Real> lin_model{};
   const Real* __restrict__ gsite = reinterpret_cast<const Real*>(sd.sites);
   const bool diag = it.i0 == it.j0;
   const int nrow = min(TJ, n - it.i0), ncol = min(TJ, n - it.j0);
@@ -446,7 +402,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     } else {
       Real r[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) r[k] = gsite[k * np + mc];
+      for (int k = 0; k < NR; ++k) r[k] = gsite[(LIN && k >= 3 ? class_reals(C) - 6 + k : k) * np + mc];
 #pragma unroll
       for (int k = 0; k < NR; ++k) u.t.site[side][k][lane] = r[k];
       if constexpr (SITE) {
@@ -520,6 +476,11 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   const int doff = incl - cnt;               // lane d: offset of diagonal d
   const int total = __builtin_amdgcn_readlane(incl, TJ - 1);
 
+  if constexpr (LIN) {
+    lin_model.c6 = s_tab.c6[0][0];
+    lin_model.c12 = s_tab.c12[0][0];
+    lin_model.K = kprod<Real>(s_tab.mqd[0][0], s_tab.mqd[0][0], E.inv_ke);
+  }
   // 2.-3. the diagonal-major list, one pair per lane, chunks dealt to waves
   double a_ulj = 0, a_uel = 0, a_us = 0, a_uss = 0;
   double a_jq[3] = {0, 0, 0};
@@ -556,23 +517,30 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     for (int k = 0; k < NR; ++k) rec[k] = u.t.site[0][k][row];
     constexpr Real z = -Real(0);             // -0 + x is x: no zeroing, no first add
     PairAcc<Real> acc{z, z, z, z, z, z};
-    SiteAcc<Real, C> ai, unused;
-    ai.zero();
-    const bool elec_in = !SITE || r2d < rc2;
-    int nlj_in = 0;
-    const double R64[3] = {dx, dy, dz};
-    eval_molecule_pair<Real, C, false, TJ, SITE, ONE>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry,
-                                                      Rz, R2, ai, unused, acc, SiteCut{R64, &u.t.lj64[0][0][row],
-                                                      &u.t.lj64[1][0][col], rc2}, elec_in, &nlj_in);
-    // interacting site pairs; in the site-site mode a listed pair counts
-    // only when at least one of its site pairs interacts
-    int ns = s_tab.nsite[spi][spj];
-    if constexpr (SITE) {
-      const int nlj2 = s_tab.cnt[spi][0] * s_tab.cnt[spj][0];
-      ns = nlj_in + (elec_in ? ns - nlj2 : 0);
-    }
     Real Fi[3] = {z, z, z}, Ti[3] = {z, z, z};
-    fold_sites<Real, C, 1, Real>(rec, ai, Fi, Ti);
+    int ns = s_tab.nsite[spi][spj];
+    if constexpr (LIN) {
+      Real recj[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) recj[k] = u.t.site[1][k][col];
+      eval_linear_pair(rec, recj, Rx, Ry, Rz, R2, lin_model, acc, Fi, Ti);
+    } else {
+      SiteAcc<Real, C> ai, unused;
+      ai.zero();
+      const bool elec_in = !SITE || r2d < rc2;
+      int nlj_in = 0;
+      const double R64[3] = {dx, dy, dz};
+      eval_molecule_pair<Real, C, false, TJ, SITE, ONE>(rec, &u.t.site[1][0][col], spi, spj, s_tab, E, Rx, Ry,
+                                                        Rz, R2, ai, unused, acc, SiteCut{R64, &u.t.lj64[0][0][row],
+                                                        &u.t.lj64[1][0][col], rc2}, elec_in, &nlj_in);
+      // interacting site pairs; in the site-site mode a listed pair counts
+      // only when at least one of its site pairs interacts
+      if constexpr (SITE) {
+        const int nlj2 = s_tab.cnt[spi][0] * s_tab.cnt[spj][0];
+        ns = nlj_in + (elec_in ? ns - nlj2 : 0);
+      }
+      fold_sites<Real, C, 1, Real>(rec, ai, Fi, Ti);
+    }
     const Real Tj[3] = {-Ti[0] - (Ry * Fi[2] - Rz * Fi[1]), -Ti[1] - (Rz * Fi[0] - Rx * Fi[2]),
                         -Ti[2] - (Rx * Fi[1] - Ry * Fi[0])};
     if (valid) {
@@ -678,23 +646,22 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
 
 // ---------------------------------------------------------------------------
 // Fixed-order reductions of the pair partials.
-//  reduce_force_kernel: one thread per molecule and component sums its
-//    partials in order, in FP64 (the partials are in the slot's Real: each is
-//    a sum of at most one tile's pair terms); grid (6 x molecule blocks,
-//    slots).  OVERWRITES force and torque.
-//  reduce_sums_kernel: one block per slot; item sums (each thread a
-//    contiguous run, then a tree), species counts, Ewald constants and the LJ
-//    tail.  OVERWRITES sums.
+//  forces: one thread per molecule and component sums its partials in
+//    order, in FP64 (the partials are in the slot's Real: each is a sum of at
+//    most one tile's pair terms).  OVERWRITES force and torque.
+//  sums: one block per slot; item sums (each thread a contiguous run, then a
+//    tree), species counts, Ewald constants and the LJ tail.  OVERWRITES sums.
+//  One launch does both (reduce_pair_kernel).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __restrict__ slots,
-                                                           const SysParams* __restrict__ prm) {
-  // one thread per (component, molecule): the grid's x holds six runs of
-  // molecule blocks, one per force/torque component, so that the largest
-  // systems' serial chains are one component long
+// one thread per (component, molecule): block bx of the slot's 6 x mb force
+// blocks, six runs of molecule blocks, one per force/torque component, so
+// that the largest systems' serial chains are one component long
+__device__ __forceinline__ void reduce_force_block(const SlotDev* __restrict__ slots,
+                                                   const SysParams* __restrict__ prm, int bx, int mb) {
   const SlotDev& sd = slots[blockIdx.y];
   if (!sd.active) return;
-  const int mb = gridDim.x / 6, c = blockIdx.x / mb;
-  const int i = (blockIdx.x - c * mb) * 256 + threadIdx.x;
+  const int c = bx / mb;
+  const int i = (bx - c * mb) * 256 + threadIdx.x;
   if (i >= sd.n) return;
   const int np = sd.npad, ld = sd.com_ld, nparts = sd.jsplits;
   const size_t stride = (size_t)6 * np;
@@ -724,13 +691,13 @@ __global__ __launch_bounds__(256) void reduce_force_kernel(const SlotDev* __rest
     sd.torque[(c - 3) * ld + i] = v;
 }
 
-__global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restrict__ slots,
-                                                          const SysParams* __restrict__ prm) {
+__device__ __forceinline__ void reduce_sums_block(const SlotDev* __restrict__ slots,
+                                                  const SysParams* __restrict__ prm, int slot) {
   __shared__ double s_red[kNumBlockSums][256];
   __shared__ int s_cnt[kMaxSp][256];
-  const SlotDev& sd = slots[blockIdx.x];
+  const SlotDev& sd = slots[slot];
   if (!sd.active) return;
-  const SysParams& P = prm[blockIdx.x];
+  const SysParams& P = prm[slot];
   const int tid = threadIdx.x, n = sd.n;
   int cnt[kMaxSp];
 #pragma unroll
@@ -827,6 +794,17 @@ __global__ __launch_bounds__(256) void reduce_sums_kernel(const SlotDev* __restr
   }
 }
 
+// Both reductions in one launch: grid (6 x molecule blocks + 1, slots); the
+// last block of each slot's row sums its work items' block sums.
+__global__ __launch_bounds__(256) void reduce_pair_kernel(const SlotDev* __restrict__ slots,
+                                                          const SysParams* __restrict__ prm) {
+  const int mb = (gridDim.x - 1) / 6;
+  if ((int)blockIdx.x < 6 * mb)
+    reduce_force_block(slots, prm, blockIdx.x, mb);
+  else
+    reduce_sums_block(slots, prm, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -866,11 +844,20 @@ static hipError_t launch_pair_cw(const WorkItem* items, int base, int count, con
 }
 
 template <typename Real, int C, bool HF, bool SITE>
-static hipError_t launch_pair_sym(bool one_species, const WorkItem* items, int base, int count,
+static hipError_t launch_pair_sym(int form, const WorkItem* items, int base, int count,
                                   const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
                                   hipStream_t st) {
+  // the linear form in FP32 only: in FP64 its 4-wave register budget spills
+  // (13.7 against 8.0 ms per step of the batched workload, measured)
+  if constexpr (C == 1 && !HF && !SITE && sizeof(Real) == 4) {
+    if (form == kFormLinear) {
+      hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE, true, true>), dim3(count), dim3(64 * kSymWaves), 0,
+                         st, items, base, slots, prm, tab);
+      return hipGetLastError();
+    }
+  }
   if constexpr (C <= 3) {
-    if (one_species) {
+    if (form != kFormGeneral) {
       hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE, true>), dim3(count), dim3(64 * kSymWaves), 0, st,
                          items, base, slots, prm, tab);
       return hipGetLastError();
@@ -882,16 +869,16 @@ static hipError_t launch_pair_sym(bool one_species, const WorkItem* items, int b
 }
 
 template <typename Real, int C>
-static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, bool one_species, const WorkItem* items,
+static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, int form, const WorkItem* items,
                                 int base, int count, const SlotDev* slots, const SysParams* prm,
                                 const SpeciesTable* tab, hipStream_t st) {
   if (waves == 0) {  // symmetric tile pairs
     if (count <= 0) return hipSuccess;
     if (site_cut)
-      return heat_flux ? launch_pair_sym<Real, C, true, true>(one_species, items, base, count, slots, prm, tab, st)
-                       : launch_pair_sym<Real, C, false, true>(one_species, items, base, count, slots, prm, tab, st);
-    return heat_flux ? launch_pair_sym<Real, C, true, false>(one_species, items, base, count, slots, prm, tab, st)
-                     : launch_pair_sym<Real, C, false, false>(one_species, items, base, count, slots, prm, tab, st);
+      return heat_flux ? launch_pair_sym<Real, C, true, true>(form, items, base, count, slots, prm, tab, st)
+                       : launch_pair_sym<Real, C, false, true>(form, items, base, count, slots, prm, tab, st);
+    return heat_flux ? launch_pair_sym<Real, C, true, false>(form, items, base, count, slots, prm, tab, st)
+                     : launch_pair_sym<Real, C, false, false>(form, items, base, count, slots, prm, tab, st);
   }
   // the heat flux and the site-site cut-off run on symmetric items only
   if (heat_flux || site_cut) return hipErrorInvalidValue;
@@ -901,14 +888,14 @@ static hipError_t launch_pair_c(int waves, bool heat_flux, bool site_cut, bool o
   return launch_pair_cw<Real, C, 1>(items, base, count, slots, prm, tab, st);
 }
 
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, int form,
                        const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st) {
 #define MS2_PAIR_CASE(C)                                                                                       \
   case C:                                                                                                      \
     return precision == MS2_FP32                                                                               \
-               ? launch_pair_c<float, C>(waves, heat_flux, site_cut, one_species, items, base, count, slots, prm, tab, st)  \
-               : launch_pair_c<double, C>(waves, heat_flux, site_cut, one_species, items, base, count, slots, prm, tab, st);
+               ? launch_pair_c<float, C>(waves, heat_flux, site_cut, form, items, base, count, slots, prm, tab, st)  \
+               : launch_pair_c<double, C>(waves, heat_flux, site_cut, form, items, base, count, slots, prm, tab, st);
   switch (cls) {
     MS2_PAIR_CASE(0)
     MS2_PAIR_CASE(1)
@@ -923,8 +910,8 @@ hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool s
 
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_force_kernel, dim3(6 * ((max_n + 255) / 256), nslots), dim3(256), 0, st, slots, prm);
-  hipLaunchKernelGGL(reduce_sums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
+  hipLaunchKernelGGL(reduce_pair_kernel, dim3(6 * ((max_n + 255) / 256) + 1, nslots), dim3(256), 0, st, slots,
+                     prm);
   return hipGetLastError();
 }
 

@@ -119,6 +119,12 @@ struct SlotDev {
   int* err;                   // device error word (1: a species index outside the table), or NULL
 };
 
+// Forms of the symmetric pair kernel, chosen per context (never per batch
+// mix): any species; one species with a site of every kind its class holds;
+// one linear two-centre LJ + quadrupole species (both LJ sites, equal, on
+// the quadrupole's axis at +-h, the quadrupole at the centre).
+enum PairForm { kFormGeneral = 0, kFormOneSpecies = 1, kFormLinear = 2 };
+
 // Species indices come from caller memory.  Every load clamps them into the
 // table so a bad index can never address outside it; the kernels that end
 // a call (the force and sum reductions, the structure factor) also test them

@@ -4,9 +4,11 @@
 //   md_wrap_kernel     wrap the uploaded centres into [0, L)
 //   md_init_kernel     Gear start-up derivatives from the first force
 //                      evaluation; kinetic energies; ACF sample at t = 0
-//   md_begin_kernel    Gear predictor (Pascal triangle) and unit-quaternion
-//                      projection, or the first velocity-Verlet kick + drift
-//   md_correct_kernel, md_thermo_kernel, md_rescale_kernel, md_sample_kernel
+//   md_begin_frame_kernel
+//                      Gear predictor (Pascal triangle) and unit-quaternion
+//                      projection, or the first velocity-Verlet kick + drift;
+//                      then the site frame of the predicted state
+//   md_correct_kernel, md_finish_kernel
 //                      the step's end: Gear corrector (5-value coefficients
 //                      for second-order translation and first-order
 //                      quaternion/Euler systems) or the second kick;
@@ -26,6 +28,7 @@
 
 #include "internal.h"
 #include "quat.h"
+#include "site_frame.h"
 
 namespace ms2 {
 
@@ -227,15 +230,9 @@ __device__ __forceinline__ void gear_predict(double (&a)[5][NC]) {
   }
 }
 
-__global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict__ slots, MDDev* md,
-                                                       const SysParams* __restrict__ prm,
-                                                       const SpeciesTable* __restrict__ tab) {
-  const SlotDev& sd = slots[blockIdx.y];
-  const MDDev& m = md[blockIdx.y];
-  if (!m.active) return;
-  const SysParams& P = prm[blockIdx.y];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= sd.n) return;
+// Predictor (Gear) or first kick and drift (velocity Verlet) of molecule i.
+__device__ __forceinline__ void md_begin_molecule(const SlotDev& sd, const MDDev& m, const SysParams& P,
+                                                  const SpeciesTable* __restrict__ tab, int i) {
   const int np = sd.com_ld;
   if (m.integrator == MS2_GEAR) {
     // every load of the molecule's state is issued before the first store
@@ -278,18 +275,38 @@ __global__ __launch_bounds__(256) void md_begin_kernel(const SlotDev* __restrict
   }
 }
 
+// Start of a step in one launch per precision: the predictor of each
+// molecule, then the site frame of the predicted state (the force path's
+// first kernel), by the same thread.  Slots of the other precision are left
+// to the other launch.
+template <typename Real, int C>
+__global__ __launch_bounds__(256) void md_begin_frame_kernel(const SlotDev* __restrict__ slots, MDDev* md,
+                                                             const SysParams* __restrict__ prm,
+                                                             const SpeciesTable* __restrict__ tab) {
+  const SlotDev& sd = slots[blockIdx.y];
+  const MDDev& m = md[blockIdx.y];
+  const SysParams& P = prm[blockIdx.y];
+  if (P.precision != (sizeof(Real) == 4 ? MS2_FP32 : MS2_FP64)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= sd.n) return;
+  if (m.active) md_begin_molecule(sd, m, P, tab, i);
+  // the site frame reads the predicted centre and quaternion this thread
+  // has just stored: no reordering of memory accesses across this point
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (sd.active) site_frame_molecule<Real, C>(sd, tab, i);
+}
+
 // ---------------------------------------------------------------------------
-// End of the step, in four launches so that the per-molecule work spreads
-// over many blocks of one system:
+// End of the step, in two launches:
 //   md_correct_kernel  (molecule blocks x slots) heat-flux kinetic part of the
 //                      predicted state when due, corrector (or second kick),
 //                      per-block fixed-order partials of sum m v^2, sum I w^2
 //                      and the heat-flux part
-//   md_thermo_kernel   (slot) partials summed in block order; isokinetic
-//                      factors; kinetic energies, totals, Lustig moments,
-//                      RDF flag, status
-//   md_rescale_kernel  (molecule blocks x slots) applies the factors
-//   md_sample_kernel   (slot) ACF sample when due; step count, end of run
+//   md_finish_kernel   (one block per slot) the partials summed in block
+//                      order; isokinetic factors; kinetic energies, totals,
+//                      Lustig moments, RDF flag, status; the factors applied
+//                      to every molecule; ACF sample when due; step count,
+//                      end of run
 // ---------------------------------------------------------------------------
 
 // fixed-order sums of NV values over the kMdBlock threads of a block; every
@@ -428,26 +445,10 @@ __global__ __launch_bounds__(kMdBlock) void md_correct_kernel(SlotDev* slots, MD
   }
 }
 
-__global__ __launch_bounds__(kMdBlock) void md_thermo_kernel(SlotDev* slots, MDDev* md,
-                                                             const SysParams* __restrict__ prm) {
-  __shared__ double red[5][kMdBlock];
-  SlotDev& sd = slots[blockIdx.x];
-  MDDev& m = md[blockIdx.x];
-  const int tid = threadIdx.x;
-  if (!m.active) {
-    // a finished slot samples nothing more (its last RDF sample was taken
-    // right after the step that ended it)
-    if (tid == 0) m.rdf_due = 0;
-    return;
-  }
-  const SysParams& P = prm[blockIdx.x];
-  // block partials: each thread a contiguous run, then the tree
-  const int nb = (sd.n + kMdBlock - 1) / kMdBlock, per = (nb + kMdBlock - 1) / kMdBlock;
-  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = tid * per; b < min(nb, (tid + 1) * per); ++b)
-    for (int k = 0; k < 5; ++k) v[k] += m.md_part[(size_t)b * 8 + k];
-  block_sums<5>(v, red);
-  if (tid != 0) return;
+// The thermostat's tail (one thread): the kinetic sums v (m v^2, I w^2, the
+// heat flux's kinetic part) give the isokinetic factors, kinetic energies,
+// Lustig moments, the RDF flag and the status.
+__device__ void thermo_tail(SlotDev& sd, MDDev& m, const SysParams& P, const double* v) {
   if (hf_due(m))
     for (int c = 0; c < 3; ++c) m.jq_now[c] = v[2 + c] + sd.jq[c];
   double k2 = v[0], kr2 = v[1], ft = 1.0, fr = 1.0;
@@ -491,20 +492,15 @@ __global__ __launch_bounds__(kMdBlock) void md_thermo_kernel(SlotDev* slots, MDD
   if (!ok) m.status = MS2_ENONFINITE;
 }
 
-__global__ __launch_bounds__(kMdBlock) void md_rescale_kernel(const SlotDev* __restrict__ slots, MDDev* md) {
-  const SlotDev& sd = slots[blockIdx.y];
-  const MDDev& m = md[blockIdx.y];
-  if (!m.active || !(m.temperature > 0.0)) return;
-  const int i = blockIdx.x * kMdBlock + threadIdx.x;
-  if (i >= sd.n) return;
-  const int np = sd.com_ld;
-  const double ft = m.scale_tr, fr = m.scale_rot;
+// The isokinetic factors applied to molecule i (velocities, the Gear
+// state's first derivatives).
+__device__ __forceinline__ void rescale_molecule(MDDev& m, int np, int i, double ft, double fr) {
   const bool gear = m.integrator == MS2_GEAR, rot = m.rotating && fr != 1.0;
   double* __restrict__ const gv = m.vel;
   double* __restrict__ const gr = m.r;
   double* __restrict__ const gw = m.w;
   double* __restrict__ const gq = m.q;
-  // all loads before the first store (see md_begin_kernel)
+  // all loads before the first store (see md_begin_molecule)
   double v[3], r1[3], w1[3], q1[4];
   for (int c = 0; c < 3; ++c) {
     v[c] = gv[c * np + i];
@@ -524,13 +520,58 @@ __global__ __launch_bounds__(kMdBlock) void md_rescale_kernel(const SlotDev* __r
   }
 }
 
-__global__ __launch_bounds__(kMdThreads) void md_sample_kernel(SlotDev* slots, MDDev* md,
+// thermostat, rescale and samplers of one slot in one block of kMdThreads
+// threads; the thermostat's sums use the first kMdBlock threads in the
+// order of md_correct_kernel's block partials (the same bits as a block of
+// kMdBlock threads)
+__global__ __launch_bounds__(kMdThreads) void md_finish_kernel(SlotDev* slots, MDDev* md,
+                                                               const SysParams* __restrict__ prm,
                                                                const SpeciesTable* __restrict__ tab) {
+  __shared__ double red5[5][kMdBlock];
   __shared__ double red[kMdThreads];
+  __shared__ double s_scale[2];
   SlotDev& sd = slots[blockIdx.x];
   MDDev& m = md[blockIdx.x];
-  if (!m.active) return;
   const int tid = threadIdx.x;
+  if (!m.active) {
+    // a finished slot samples nothing more (its last RDF sample was taken
+    // right after the step that ended it)
+    if (tid == 0) m.rdf_due = 0;
+    return;
+  }
+  const SysParams& P = prm[blockIdx.x];
+  // 1. block partials: each of the first kMdBlock threads a contiguous run,
+  //    then the tree
+  {
+    const int nb = (sd.n + kMdBlock - 1) / kMdBlock, per = (nb + kMdBlock - 1) / kMdBlock;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (tid < kMdBlock) {
+      for (int b = tid * per; b < min(nb, (tid + 1) * per); ++b)
+        for (int k = 0; k < 5; ++k) v[k] += m.md_part[(size_t)b * 8 + k];
+      for (int k = 0; k < 5; ++k) red5[k][tid] = v[k];
+    }
+    __syncthreads();
+    for (int h = kMdBlock / 2; h > 0; h >>= 1) {
+      if (tid < h)
+        for (int k = 0; k < 5; ++k) red5[k][tid] += red5[k][tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      for (int k = 0; k < 5; ++k) v[k] = red5[k][0];
+      thermo_tail(sd, m, P, v);
+      s_scale[0] = m.scale_tr;
+      s_scale[1] = m.scale_rot;
+    }
+    __syncthreads();
+  }
+  // 2. the isokinetic factors applied to every molecule
+  if (m.temperature > 0.0) {
+    const int np = sd.com_ld, n = sd.n;
+    const double ft = s_scale[0], fr = s_scale[1];
+    for (int i = tid; i < n; i += kMdThreads) rescale_molecule(m, np, i, ft, fr);
+  }
+  __syncthreads();
+  // 3. samplers and the step count
   const long long s = m.steps_done + 1;
   if (m.acf_every > 0 && s % m.acf_every == 0) {
     acf_sample(m, tab, sd, m.vel, sd.com_ld, s, red, true);
@@ -822,21 +863,38 @@ hipError_t launch_md_init(SlotDev* slots, MDDev* md, const SpeciesTable* tab, in
   return hipGetLastError();
 }
 
-hipError_t launch_md_begin(const SlotDev* slots, MDDev* md, const SysParams* prm,
-                           const SpeciesTable* tab, int nslots, int max_n, hipStream_t st) {
-  hipLaunchKernelGGL(md_begin_kernel, dim3((max_n + 255) / 256, nslots), dim3(256), 0, st, slots, md,
-                     prm, tab);
-  return hipGetLastError();
-}
-
 hipError_t launch_md_end(SlotDev* slots, MDDev* md, const SysParams* prm, const SpeciesTable* tab,
                          int nslots, int max_n, hipStream_t st) {
   const int mb = (max_n + kMdBlock - 1) / kMdBlock;
   hipLaunchKernelGGL(md_correct_kernel, dim3(mb, nslots), dim3(kMdBlock), 0, st, slots, md, prm, tab);
-  hipLaunchKernelGGL(md_thermo_kernel, dim3(nslots), dim3(kMdBlock), 0, st, slots, md, prm);
-  hipLaunchKernelGGL(md_rescale_kernel, dim3(mb, nslots), dim3(kMdBlock), 0, st, slots, md);
-  hipLaunchKernelGGL(md_sample_kernel, dim3(nslots), dim3(kMdThreads), 0, st, slots, md, tab);
+  hipLaunchKernelGGL(md_finish_kernel, dim3(nslots), dim3(kMdThreads), 0, st, slots, md, prm, tab);
   return hipGetLastError();
+}
+
+template <typename Real, int C>
+static hipError_t launch_begin_frame_c(const SlotDev* slots, MDDev* md, const SysParams* prm,
+                                       const SpeciesTable* tab, int nslots, int max_n, hipStream_t st) {
+  hipLaunchKernelGGL((md_begin_frame_kernel<Real, C>), dim3((max_n + 255) / 256, nslots), dim3(256), 0, st, slots,
+                     md, prm, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_begin_frame(int cls, int precision, const SlotDev* slots, MDDev* md, const SysParams* prm,
+                                 const SpeciesTable* tab, int nslots, int max_n, hipStream_t st) {
+#define MS2_BEGIN_CASE(C)                                                                             \
+  case C:                                                                                             \
+    return precision == MS2_FP32 ? launch_begin_frame_c<float, C>(slots, md, prm, tab, nslots, max_n, st) \
+                                 : launch_begin_frame_c<double, C>(slots, md, prm, tab, nslots, max_n, st);
+  switch (cls) {
+    MS2_BEGIN_CASE(0)
+    MS2_BEGIN_CASE(1)
+    MS2_BEGIN_CASE(2)
+    MS2_BEGIN_CASE(3)
+    MS2_BEGIN_CASE(4)
+    MS2_BEGIN_CASE(5)
+  }
+#undef MS2_BEGIN_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_rdf(int waves, const WorkItem* items, int base, int count, const SlotDev* slots,

@@ -36,7 +36,7 @@
 namespace ms2 {
 hipError_t launch_site_frame(int cls, int precision, const SlotDev* slots, const SysParams* prm,
                              const SpeciesTable* tab, int nslots, int max_n, hipStream_t st);
-hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, bool one_species,
+hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool site_cut, int form,
                        const WorkItem* items, int base, int count, const SlotDev* slots, const SysParams* prm,
                        const SpeciesTable* tab, hipStream_t st);
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
@@ -183,7 +183,7 @@ extern "C" ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_param
   MS2_NA_HIP(hipGetLastError());
   MS2_NA_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n, st));
   MS2_NA_HIP(launch_pair(ctx->cls, h_params->precision, 0, false, h_params->cutoff_mode == MS2_CUT_SITE,
-                         single_species_form(ctx), items, 0, nitems, r->d_slot, r->d_prm, ctx->d_tab, st));
+                         pair_form(ctx), items, 0, nitems, r->d_slot, r->d_prm, ctx->d_tab, st));
   MS2_NA_HIP(launch_reduce_pair(r->d_slot, r->d_prm, 1, n, st));
   MS2_NA_HIP(hipEventRecord(r->ev, st));
 #undef MS2_NA_HIP

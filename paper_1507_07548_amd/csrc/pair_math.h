@@ -627,6 +627,99 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Linear two-centre LJ + quadrupole molecules (one species): both LJ sites on
+// the quadrupole's axis, at +d and -d from the centre (the site frame gives
+// the second offset as the exact negation of the first), equal LJ
+// coefficients, the quadrupole at the centre.  With d_i, d_j the lab offsets
+// of the first LJ site of each molecule, the four LJ site pairs have
+// separations R + delta, delta = +-(d_i - d_j) or +-(d_i + d_j), so two
+// difference vectors give every |r|^2 = |R|^2 + (2 R.delta + delta.delta)
+// and r.R = |R|^2 + R.delta -- the same values, bit for bit, as
+// site_separation forms from the four site pairs one by one.  The pairs'
+// forces and torques collapse onto the vectors R, d_i, d_j:
+//   F_i   = -(sum u'/r) R - (E_m + E_p) d_i + (E_m - E_p) d_j
+//   tau_i = d_i x (sum_a s_a f_a) = -(E_m + E_p) (d_i x R) + (S_m - S_p) (d_i x d_j)
+// with E_m = u'/r(++) - u'/r(--), S_m = u'/r(++) + u'/r(--) and E_p, S_p
+// the same for (+-), (-+).  The quadrupole pair (r = R, n = R / |R|,
+// c_a = e_i.n, c_b = e_j.n, c_ab = e_i.e_j) adds
+// A [(5 P + P_a c_a + P_b c_b) n - P_a e_i - P_b e_j] (A = K |R|^-6) to F_i
+// and e_i x g_i, g_i = -K |R|^-5 (P_a n + P_c e_j), to tau_i.  No constant of
+// the geometry (h) enters: every rounding is per molecule, as in the general
+// form.  The caller takes tau_j from tau_i + tau_j + R x F_i = 0.
+template <typename Real>
+struct LinearModel {
+  Real c6, c12, K;   // LJ coefficients, k_e Q^2
+};
+
+// ri, rj: the staged record of each molecule, [d (first LJ site), e (axis)]
+template <typename Real>
+__device__ __forceinline__ void eval_linear_pair(const Real* ri, const Real* rj, Real Rx, Real Ry, Real Rz,
+                                                 Real R2, const LinearModel<Real>& M, PairAcc<Real>& acc,
+                                                 Real* F, Real* T) {
+  const Real* di = ri;
+  const Real* ei = ri + 3;
+  const Real* dj = rj;
+  const Real* ej = rj + 3;
+  const Real mx = di[0] - dj[0], my = di[1] - dj[1], mz = di[2] - dj[2];   // delta(++)
+  const Real px = di[0] + dj[0], py = di[1] + dj[1], pz = di[2] + dj[2];   // delta(+-)
+  const Real Rm = Rx * mx + Ry * my + Rz * mz, mm = mx * mx + my * my + mz * mz;
+  const Real Rp = Rx * px + Ry * py + Rz * pz, pp = px * px + py * py + pz * pz;
+  // (s_a, s_b) = (+,+), (-,-), (+,-), (-,+)
+  const Real Rd[4] = {Rm, -Rm, Rp, -Rp};
+  const Real dd[4] = {mm, mm, pp, pp};
+  constexpr Real z = -Real(0);
+  Real dur[4], ulj = z, uss = z;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const Real r2 = R2 + (Real(2) * Rd[k] + dd[k]);
+    const Real rR = R2 + Rd[k];
+    const Real ir2 = rcp_(r2);
+    const Real ir6 = ir2 * ir2 * ir2;
+    const Real t6 = M.c6 * ir6;
+    const Real t12 = M.c12 * ir6 * ir6;
+    dur[k] = (Real(6) * t6 - Real(12) * t12) * ir2;             // u'/r
+    const Real d2u = (Real(156) * t12 - Real(42) * t6) * ir2;   // u''
+    ulj += t12 - t6;
+    uss += (d2u - dur[k]) * (rR * rR * ir2) + dur[k] * R2;
+  }
+  const Real Em = dur[0] - dur[1], Sm = dur[0] + dur[1];
+  const Real Ep = dur[2] - dur[3], Sp = dur[2] + dur[3];
+
+  const Real ir = rsq_(R2);
+  const Real ca = (Rx * ei[0] + Ry * ei[1] + Rz * ei[2]) * ir;
+  const Real cb = (Rx * ej[0] + Ry * ej[1] + Rz * ej[2]) * ir;
+  const Real cab = ei[0] * ej[0] + ei[1] * ej[1] + ei[2] * ej[2];
+  const Poly<Real> q = mp_poly<Real, 3, 3>(ca, cb, cab);
+  const Real irr = ir * ir;
+  const Real Kp = M.K * (irr * irr * ir);                         // K |R|^-5
+  const Real uq = Kp * q.P;
+  const Real A = Kp * ir;
+  const Real sdot = Real(5) * q.P + q.Pa * ca + q.Pb * cb;
+  acc.ulj = ulj;
+  acc.uel = uq;
+  acc.uss = uss + Real(30) * uq;
+  // F_i = cR R + cd_i d_i + cd_j d_j - A P_a e_i - A P_b e_j
+  const Real cR = A * sdot * ir - (Sm + Sp);
+  const Real cdi = -(Em + Ep), cdj = Em - Ep;
+  const Real cei = -A * q.Pa, cej = -A * q.Pb;
+  F[0] = cR * Rx + cdi * di[0] + cdj * dj[0] + cei * ei[0] + cej * ej[0];
+  F[1] = cR * Ry + cdi * di[1] + cdj * dj[1] + cei * ei[1] + cej * ej[1];
+  F[2] = cR * Rz + cdi * di[2] + cdj * dj[2] + cei * ei[2] + cej * ej[2];
+  acc.fx = F[0];
+  acc.fy = F[1];
+  acc.fz = F[2];
+  // tau_i = d_i x V + e_i x W, V = -(E_m + E_p) R + (S_m - S_p) d_j,
+  // W = -K |R|^-5 (P_a R / |R| + P_c e_j)
+  const Real vs = Sm - Sp;
+  const Real Vx = cdi * Rx + vs * dj[0], Vy = cdi * Ry + vs * dj[1], Vz = cdi * Rz + vs * dj[2];
+  const Real wa = -Kp * q.Pa * ir, wc = -Kp * q.Pc;
+  const Real Wx = wa * Rx + wc * ej[0], Wy = wa * Ry + wc * ej[1], Wz = wa * Rz + wc * ej[2];
+  T[0] = (di[1] * Vz - di[2] * Vy) + (ei[1] * Wz - ei[2] * Wy);
+  T[1] = (di[2] * Vx - di[0] * Vz) + (ei[2] * Wx - ei[0] * Wz);
+  T[2] = (di[0] * Vy - di[1] * Vx) + (ei[0] * Wy - ei[1] * Wx);
+}
+
 // Force and torque of one molecule from its per-site accumulators:
 // F = sum f, tau = sum d x f + e x g (d, e from the molecule's record, read
 // with stride STRIDE).  Accumulates into F and T, of type Out.

@@ -408,3 +408,36 @@ def test_centres_on_the_box_faces():
     f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, ctx=symmetric_ctx(s, ms2.FP64), label="centres on faces")
     assert ef < 1e-11 and et < 1e-11, (ef, et)
     check_sums(su, so, 1e-11, 1e-12)
+
+
+# --------------------------------------------------------------------------
+# the linear two-centre form of the pair kernel and the general forms
+# --------------------------------------------------------------------------
+def two_centre_variants():
+    """The 2CLJQ molecule (linear: both LJ sites on the quadrupole axis, the
+    kernel's linear form), the same with one LJ site moved by 1e-9 along the
+    axis (not symmetric: the general single-species form) and with the LJ
+    sites across the quadrupole axis (off the axis: general form)."""
+    lin = I.two_center_lj_quadrupole()
+    asym = I.two_center_lj_quadrupole()
+    asym.sites[1] = I.Site(I.LJ, (0.0, 0.0, -0.15 - 1e-9), sigma=1.0, eps=1.0)
+    across = I.two_center_lj_quadrupole()
+    across.sites[0] = I.Site(I.LJ, (0.15, 0.0, 0.0), sigma=1.0, eps=1.0)
+    across.sites[1] = I.Site(I.LJ, (-0.15, 0.0, 0.0), sigma=1.0, eps=1.0)
+    return {"linear": lin, "asymmetric": asym, "across_axis": across}
+
+
+@pytest.mark.parametrize("name", ["linear", "asymmetric", "across_axis"])
+@pytest.mark.parametrize("n", [130, 1000])
+def test_two_centre_forms_match_the_oracle(name, n):
+    sp = two_centre_variants()[name]
+    s = I.jittered(I.quadrupolar_fluid(n=n, density=0.6), 0.1, seed=n)
+    s.species = [sp]
+    for prec, tol in [(ms2.FP64, 1e-11), (ms2.FP32, 1e-5)]:
+        f, t, su, fo, to, so, ef, et = compare(s, prec, label=f"two-centre {name}")
+        say(f"  max|dF|/rms {ef:.2e}  max|dT|/rms {et:.2e}")
+        assert ef < tol and et < tol, (ef, et)
+        if prec == ms2.FP64:
+            check_sums(su, so, 1e-11, 1e-12)
+        else:
+            assert energy_error(su, so) < 1e-6      # jittered lattice starts (coherent rounding)

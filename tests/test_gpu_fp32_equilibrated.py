@@ -72,7 +72,7 @@ MODELS = {
 
 # (|dU|/|U|, |dW|/|W| and |dU_s|/|U_s|, |dU_ss|/|U_ss|) asserted per state
 TOL = {
-    "quad": (2e-9, 1e-7, 2e-8),
+    "quad": (2e-9, 2e-7, 2e-8),
     "quad_lo": (2e-8, 1e-6, 1e-7),
     "ionic": (1e-7, 5e-7, 1e-7),
     "lj": (1e-8, 2e-7, 5e-8),
