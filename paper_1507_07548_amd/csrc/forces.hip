@@ -693,8 +693,10 @@ __device__ __forceinline__ void reduce_force_block(const SlotDev* __restrict__ s
 
 __device__ __forceinline__ void reduce_sums_block(const SlotDev* __restrict__ slots,
                                                   const SysParams* __restrict__ prm, int slot) {
-  __shared__ double s_red[kNumBlockSums][256];
-  __shared__ int s_cnt[kMaxSp][256];
+  // per-wave totals only (a few hundred bytes): the launch's force blocks
+  // share this kernel's static LDS size, so the sums keep it small
+  __shared__ double s_red[4][kNumBlockSums];
+  __shared__ int s_cnt[4][kMaxSp];
   const SlotDev& sd = slots[slot];
   if (!sd.active) return;
   const SysParams& P = prm[slot];
@@ -744,39 +746,51 @@ __device__ __forceinline__ void reduce_sums_block(const SlotDev* __restrict__ sl
 #pragma unroll
       for (int k = 0; k < kNumBlockSums; ++k) acc[k] += sd.bsum[(size_t)t * kNumBlockSums + k];
   }
+  // the 64 lanes of each wave in butterfly order (a fixed order), then the
+  // four waves' totals in wave order
 #pragma unroll
-  for (int k = 0; k < kNumBlockSums; ++k) s_red[k][tid] = acc[k];
+  for (int h = 32; h > 0; h >>= 1) {
 #pragma unroll
-  for (int x = 0; x < kMaxSp; ++x) s_cnt[x][tid] = cnt[x];
+    for (int k = 0; k < kNumBlockSums; ++k) acc[k] += __shfl_xor(acc[k], h, 64);
+#pragma unroll
+    for (int x = 0; x < kMaxSp; ++x) cnt[x] += __shfl_xor(cnt[x], h, 64);
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kNumBlockSums; ++k) s_red[wave][k] = acc[k];
+#pragma unroll
+    for (int x = 0; x < kMaxSp; ++x) s_cnt[wave][x] = cnt[x];
+  }
   const bool any_bad = __syncthreads_or(bad);
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-      for (int k = 0; k < kNumBlockSums; ++k) s_red[k][tid] += s_red[k][tid + h];
-      for (int x = 0; x < kMaxSp; ++x) s_cnt[x][tid] += s_cnt[x][tid + h];
-    }
-    __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < kNumBlockSums; ++k)
+      s_red[0][k] = ((s_red[0][k] + s_red[1][k]) + s_red[2][k]) + s_red[3][k];
+#pragma unroll
+    for (int x = 0; x < kMaxSp; ++x) s_cnt[0][x] = s_cnt[0][x] + s_cnt[1][x] + s_cnt[2][x] + s_cnt[3][x];
   }
   if (tid == 0) {
     double* out = sd.sums;
     // row-owned items evaluate every pair from both sides; symmetric ones once
     const double h = sd.symmetric ? 1.0 : 0.5;
     out[MS2_SUM_U_LJ] = h * s_red[0][0];
-    out[MS2_SUM_U_ELEC] = h * s_red[1][0];
-    out[MS2_SUM_US] = h * s_red[2][0];
-    out[MS2_SUM_VIRIAL] = -h * s_red[2][0];
-    out[MS2_SUM_USS] = h * s_red[3][0];
-    out[MS2_SUM_NPAIR] = h * s_red[4][0];
-    out[MS2_SUM_NSITE] = h * s_red[5][0];
+    out[MS2_SUM_U_ELEC] = h * s_red[0][1];
+    out[MS2_SUM_US] = h * s_red[0][2];
+    out[MS2_SUM_VIRIAL] = -h * s_red[0][2];
+    out[MS2_SUM_USS] = h * s_red[0][3];
+    out[MS2_SUM_NPAIR] = h * s_red[0][4];
+    out[MS2_SUM_NSITE] = h * s_red[0][5];
     out[MS2_SUM_U_RECIP] = 0.0;
     if (sd.jq)
-      for (int c = 0; c < 3; ++c) sd.jq[c] = s_red[6 + c][0];
+      for (int c = 0; c < 3; ++c) sd.jq[c] = s_red[0][6 + c];
     double uc = 0.0, ul = 0.0, usl = 0.0, ussl = 0.0;
     for (int a = 0; a < P.nsp; ++a) {
-      const double na = (double)s_cnt[a][0];
+      const double na = (double)s_cnt[0][a];
       if (P.elec == MS2_ELEC_EWALD) uc += na * P.ew_const[a];
       if (P.lrc)
         for (int b = 0; b < P.nsp; ++b) {
-          const double nab = na * (double)s_cnt[b][0];
+          const double nab = na * (double)s_cnt[0][b];
           ul += nab * P.lrc_u[a][b];
           usl += nab * P.lrc_us[a][b];
           ussl += nab * P.lrc_uss[a][b];

@@ -14,6 +14,10 @@
       device idle time between kernels over the last <steps> steps of a
       run: a step starts at a dispatch of the marker kernel (one per step);
       prints per step the span, the kernels' busy time and the idle rest.
+  flops <f32.csv> <kernel substring> <molecule pairs per launch>
+      executed FP32 FLOP per molecule pair of the largest-grid launches from
+      a --pmc run of SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 (per wave
+      instruction: 64 lanes; an FMA counts 2); prints the field bench.py reads.
   traffic <fetch.csv> <write.csv> <copy_bytes> <kernel substring>
       HBM bytes per launch of the largest-grid dispatches whose name holds
       the substring, from two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
@@ -28,7 +32,7 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PAIR_SOURCES = ["csrc/forces.hip", "csrc/pair_math.h", "csrc/internal.h"]
+PAIR_SOURCES = ["csrc/forces.hip", "csrc/pair_math.h", "csrc/internal.h", "csrc/site_frame.h", "csrc/quat.h"]
 
 
 def pair_kernel_source_hash():
@@ -163,6 +167,36 @@ def counters(csv_path, substring):
     return "\n".join(lines)
 
 
+def flops(csv_path, substring, mol_pairs):
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        if substring not in r["Kernel_Name"]:
+            continue
+        d = per.setdefault(r["Dispatch_Id"], [int(r["Grid_Size"]), {}])
+        d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no dispatch of a kernel named like {substring!r}")
+    gmax = max(d[0] for d in per.values())
+    big = [d[1] for d in per.values() if d[0] == gmax]
+    avg = {k: sum(b.get(k, 0.0) for b in big) / len(big) for k in big[0]}
+    w = {"SQ_INSTS_VALU_ADD_F32": 1, "SQ_INSTS_VALU_MUL_F32": 1, "SQ_INSTS_VALU_FMA_F32": 2,
+         "SQ_INSTS_VALU_TRANS_F32": 1}
+    missing = [k for k in w if k not in avg]
+    if missing:
+        raise SystemExit(f"counters missing: {missing}")
+    lanes = 64.0
+    flop = sum(w[k] * avg[k] for k in w) * lanes
+    inst = sum(avg[k] for k in w) * lanes
+    lines = [f"{len(big)} launches of grid {gmax} work-items; {mol_pairs:.6g} molecule pairs per launch.", "",
+             "| counter | per launch | per molecule pair (x 64 lanes) |", "|---|---|---|"]
+    for k in sorted(w):
+        lines.append(f"| {k} | {avg[k]:.6g} | {avg[k] * lanes / mol_pairs:.1f} |")
+    lines += ["", f"- fp32_instructions_per_mol_pair: {inst / mol_pairs:.1f}",
+              f"- fp32_flop_per_mol_pair_executed: {flop / mol_pairs:.1f}",
+              f"- source_sha256: `{pair_kernel_source_hash()}`"]
+    return "\n".join(lines)
+
+
 def traffic(fetch_csv, write_csv, copy_bytes, substring):
     fd, wd = _dispatches(fetch_csv, "FETCH_SIZE"), _dispatches(write_csv, "WRITE_SIZE")
     f_kib, nf, name = _per_launch(fd, substring)
@@ -189,6 +223,8 @@ if __name__ == "__main__":
         print(counters(sys.argv[2], sys.argv[3]))
     elif len(sys.argv) >= 2 and sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5]))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "flops":
+        print(flops(sys.argv[2], sys.argv[3], float(sys.argv[4])))
     elif len(sys.argv) >= 2 and sys.argv[1] == "gaps":
         g = gaps(sys.argv[2], sys.argv[3], int(sys.argv[4]))
         print(f"per step over the last {sys.argv[4]} steps: span {g['span_us']:.1f} us, kernels busy "

@@ -120,3 +120,21 @@ def test_gaps_per_step_over_the_last_steps(tmp_path):
     assert g["idle_frac"] == pytest.approx(15.0 / 145.0)
     with pytest.raises(SystemExit):
         R.gaps(str(tmp_path / "g.db"), "pair_sym_kernel", 5)
+
+
+def test_flops_weights_each_fp32_counter(tmp_path):
+    """FMA counts two operations, ADD, MUL and TRANS one; per wave
+    instruction 64 lanes; averaged over the largest-grid launches."""
+    names = ["SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_TRANS_F32"]
+    path = str(tmp_path / "f.csv")
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, grid, vals in ((1, 1000, (10, 20, 30, 4)), (2, 1000, (10, 20, 30, 4)), (3, 8, (1e6, 0, 0, 0))):
+            for name, v in zip(names, vals):
+                w.writerow({"Dispatch_Id": d, "Kernel_Name": SYM, "Grid_Size": grid, "Counter_Name": name,
+                            "Counter_Value": v})
+    out = R.flops(path, "pair_sym_kernel<float", 64.0)
+    # (10 + 20 + 2 * 30 + 4) x 64 / 64 pairs = 94 FLOP, (10 + 20 + 30 + 4) = 64 instructions
+    assert "- fp32_flop_per_mol_pair_executed: 94.0" in out
+    assert "- fp32_instructions_per_mol_pair: 64.0" in out
