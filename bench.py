@@ -123,7 +123,7 @@ def cpu_baseline(max_procs=16, steps=8):
             "single_thread_value": single, "host_cpu": model, "host_cpus_available": avail}
 
 
-def serve_run(n_requests, n_steps, rate, window, label):
+def serve_run(n_requests, n_steps, rate, window, label, max_inflight):
     """The serving form: Poisson arrivals, models uniform over {one-site LJ,
     2CLJQ, water + 10 % ions with Ewald}, N log-uniform in [256, 8192], each
     request running `n_steps` steps with RDF (400 bins), Lustig moments
@@ -132,15 +132,17 @@ def serve_run(n_requests, n_steps, rate, window, label):
     import torch
 
     from paper_1507_07548_amd import inputs, ms2
-    from paper_1507_07548_amd.serve import GpuBackend, Request, Server, percentile
+    from paper_1507_07548_amd.serve import GpuBackend, Request, Server, backend_key, percentile
     trace = inputs.serving_trace(n_requests=n_requests, rate=rate, seed=5, n_steps=n_steps,
                                  window=window, acf_every=10, origin_every=100 if window >= 1000 else 50)
     fam = {"lj": [inputs.one_center_lj()], "2cljq": [inputs.two_center_lj_quadrupole()],
            "ionic": [inputs.water_tip4p_like(), inputs.cation(), inputs.anion()]}
-    backends = {m: GpuBackend(fam[m], max_slots=64) for m in fam}
-    reqs = [Request(r, t, m, s, ms2.FP32) for r, (t, m, s) in enumerate(trace)]
+    # one batch (context, slots, stream) per model family and size class
+    keys = sorted({backend_key(m, s.n) for _, m, s in trace})
+    backends = {k: GpuBackend(fam[k.split("/")[0]], max_slots=64) for k in keys}
+    reqs = [Request(r, t, backend_key(m, s.n), s, ms2.FP32) for r, (t, m, s) in enumerate(trace)]
     log(f"[bench] serving ({label}): {len(reqs)} requests x {n_steps} steps at {rate:.3g}/s")
-    srv = Server(backends, hbm_budget=64 << 30, chunk_steps=50, keep_samples=False)
+    srv = Server(backends, hbm_budget=64 << 30, chunk_steps=50, keep_samples=False, max_inflight=max_inflight)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = srv.run(reqs)
@@ -153,24 +155,25 @@ def serve_run(n_requests, n_steps, rate, window, label):
     return {"requests": len(res), "steps_per_request": n_steps, "acf_window_steps": window,
             "arrival_rate_per_s": rate, "p50_latency_s": percentile(lat, 50),
             "p99_latency_s": percentile(lat, 99), "md_steps_per_s": steps / makespan,
-            "makespan_s": makespan, "all_ok": all(r.status == 0 for r in res), "n_range": [256, 8192]}
+            "makespan_s": makespan, "all_ok": all(r.status == 0 for r in res), "n_range": [256, 8192],
+            "batches": keys, "max_inflight": max_inflight}
 
 
-def serving(n_requests, n_steps, window, sustained_requests, scaled):
+def serving(n_requests, n_steps, window, sustained_requests, scaled, max_inflight):
     """Two runs at the configured request size: the workload's own trace at
     50 requests/s (an overload: latency includes queueing), then a run at
     0.7 x the capacity that run measured (system-steps/s / steps per
     request); plus, optionally, the short-request trace of earlier versions."""
     out = {"models": ["1CLJ (VV NVE)", "2CLJQ (Gear NVT, RF)", "water+ions (Gear NVT, Ewald)"]}
-    full = serve_run(n_requests, n_steps, 50.0, window, "trace at 50/s")
+    full = serve_run(n_requests, n_steps, 50.0, window, "trace at 50/s", max_inflight)
     capacity = full["md_steps_per_s"] / n_steps
     out["trace_50_per_s"] = full
     out["capacity_requests_per_s"] = capacity
     if sustained_requests > 0:
         out["sustained_0p7_capacity"] = serve_run(sustained_requests, n_steps, 0.7 * capacity, window,
-                                                  "0.7 x capacity")
+                                                  "0.7 x capacity", max_inflight)
     if scaled:
-        sc = serve_run(n_requests, 400, 50.0, 200, "scaled")
+        sc = serve_run(n_requests, 400, 50.0, 200, "scaled", max_inflight)
         sc["note"] = "scaled requests (400 steps, 200-step window), kept for comparison with earlier lines"
         out["scaled_400_steps"] = sc
     return out
@@ -297,6 +300,8 @@ CASES = {
     # lone systems of the serving mix, advanced by graph replay (FP32)
     "lone_2cljq_256": lambda I: I.quadrupolar_fluid(n=256, density=0.6),
     "lone_2cljq_1000": lambda I: I.quadrupolar_fluid(n=1000, density=0.6),
+    "lone_2cljq_4000": lambda I: I.quadrupolar_fluid(n=4000, density=0.6),
+    "lone_2cljq_8192": lambda I: I.quadrupolar_fluid(n=8192, density=0.6),
     "lone_ionic_1000": lambda I: I.ionic_solution(),
 }
 
@@ -344,6 +349,9 @@ def main():
     ap.add_argument("--serve-window", type=int, default=1000)
     ap.add_argument("--serve-sustained-requests", type=int, default=24)
     ap.add_argument("--serve-scaled", action="store_true", help="also run the 400-step request trace")
+    ap.add_argument("--serve-inflight", type=int, default=3,
+                    help="batches with a chunk on the device at once, launched shortest remaining work "
+                         "first (0: no limit, every batch launches)")
     ap.add_argument("--windows", type=int, default=WINDOWS, help="timed windows of K steps (median reported)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the batched steps directly instead of through a hipGraph")
@@ -447,7 +455,8 @@ def main():
     ewald = None if args.no_ewald else ionic_form(ms2, torch, inputs, K, W)
     ctx.close()
     serve = None if args.no_serve else serving(args.serve_requests, args.serve_steps, args.serve_window,
-                                               args.serve_sustained_requests, args.serve_scaled)
+                                               args.serve_sustained_requests, args.serve_scaled,
+                                               args.serve_inflight or None)
 
     line = {
         "metric": METRIC,

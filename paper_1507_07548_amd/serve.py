@@ -14,10 +14,20 @@ stream), and every family progresses on its own: the loop repeatedly
      requests only.  A request that can never run -- larger than the whole
      budget, or refused by its backend while nothing at all is running -- is
      returned at once as a failed result with the backend's status;
-  3. launch: every idle family with active slots starts its next chunk of
-     `chunk_steps` steps on its stream, so that the families' kernels
-     overlap on the device and a new arrival waits at most for its own
-     family's chunk.
+  3. launch: idle families with active slots start their next chunk of
+     `chunk_steps` steps on their own streams.  Without a limit every idle
+     family launches, so the families' kernels overlap on the device.  With
+     `max_inflight` = k, at most k families have a chunk on the device, and
+     the idle ones launch in order of estimated remaining work, shortest
+     first: the remaining steps of the family's nearest request times the
+     family's cost per step, the sum of `cost(request)` (default n^2, the
+     pair count) over its running requests.  Shortest-remaining-work order
+     minimises the mean completion time of a set of jobs; it matters here
+     because the kernels of a batch of large systems fill every compute
+     unit, so a batch of small systems on another stream gains little from
+     running beside them and would otherwise finish at the large ones'
+     pace.  The order is revised at every chunk boundary, the only place a
+     family can be held back.
 Latency of a request = completion time - arrival time (wall clock).
 
 Backends expose footprint / admit / active / launch / ready / poll / collect
@@ -118,8 +128,13 @@ class Server:
     def __init__(self, backends: Dict[str, Any], hbm_budget: int, chunk_steps: int = 100,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep, keep_samples: bool = True,
-                 poll_s: float = 2e-4):
+                 poll_s: float = 2e-4, max_inflight: Optional[int] = None,
+                 cost: Callable[[Request], float] = lambda r: float(r.system.n) ** 2):
+        if max_inflight is not None and max_inflight < 1:
+            raise ValueError("max_inflight must be >= 1 (or None for no limit)")
         self.backends = backends
+        self.max_inflight = max_inflight
+        self.cost = cost
         self.budget = hbm_budget
         self.chunk = chunk_steps
         self.clock = clock
@@ -130,7 +145,7 @@ class Server:
 
     def run(self, requests: List[Request]) -> List[Result]:
         pending: List[Request] = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        running: Dict[tuple, tuple] = {}     # (model, slot) -> (request, footprint, admitted)
+        running: Dict[tuple, list] = {}      # (model, slot) -> [request, footprint, admitted, steps launched]
         inflight = set()                      # families with a chunk on the device
         used = 0
         results: List[Result] = []
@@ -152,7 +167,7 @@ class Server:
                 for slot, steps, status, done in be.poll():
                     if not done:
                         continue
-                    r, fp, adm = running.pop((model, slot))
+                    r, fp, adm, _ = running.pop((model, slot))
                     samples = be.collect(slot) if self.keep_samples else None
                     be.retire(slot)
                     used -= fp
@@ -192,16 +207,22 @@ class Server:
                     keep.append(r)
                     continue
                 used += fp
-                running[(r.model, slot)] = (r, fp, self.clock() - t0)
+                running[(r.model, slot)] = [r, fp, self.clock() - t0, 0]
                 self.log.append((self.clock() - t0, "admit", r.rid))
                 progressed = True
             pending = keep
-            # 3. every idle family with work starts its next chunk
-            for model, be in self.backends.items():
-                if model not in inflight and be.active():
-                    be.launch(self.chunk)
-                    inflight.add(model)
-                    progressed = True
+            # 3. idle families with work start their next chunk
+            idle = [m for m, be in self.backends.items() if m not in inflight and be.active()]
+            if self.max_inflight is not None:
+                idle.sort(key=lambda m: self._remaining_work(m, running))
+                idle = idle[:max(0, self.max_inflight - len(inflight))]
+            for model in idle:
+                self.backends[model].launch(self.chunk)
+                inflight.add(model)
+                for key, entry in running.items():
+                    if key[0] == model:
+                        entry[3] += self.chunk
+                progressed = True
             if not running and pending:
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
@@ -210,6 +231,31 @@ class Server:
             if not progressed:
                 self.sleep(self.poll_s)
         return results
+
+    def _remaining_work(self, model: str, running: Dict[tuple, list]) -> float:
+        """Estimated work until the family's nearest request completes: its
+        remaining steps (requested - launched) times the family's cost per
+        step.  Slots of a batch step in lockstep, so every running request of
+        the family pays that cost for every step."""
+        entries = [e for key, e in running.items() if key[0] == model]
+        if not entries:
+            return float("inf")
+        per_step = sum(self.cost(e[0]) for e in entries)
+        nearest = min(max(1, e[0].system.md.n_steps - e[3]) for e in entries)
+        return nearest * per_step
+
+
+# upper bounds (exclusive) of the small and medium size classes, in molecules
+SIZE_CLASSES = (1024, 4096)
+
+
+def backend_key(model: str, n: int) -> str:
+    """The batch a request of `model` with n molecules joins: one per model
+    family and size class.  The slots of a batch step in lockstep, so a small
+    request sharing a batch with a large one would finish at the large one's
+    pace; with a batch per size class it runs at its own."""
+    c = "s" if n < SIZE_CLASSES[0] else ("m" if n < SIZE_CLASSES[1] else "l")
+    return f"{model}/{c}"
 
 
 def percentile(values, q: float) -> float:

@@ -175,3 +175,80 @@ def test_nearest_rank_percentiles():
     v = list(range(1, 101))
     assert percentile(v, 50) == 50 and percentile(v, 99) == 99 and percentile(v, 100) == 100
     assert percentile([3.0], 99) == 3.0
+
+
+def test_requests_join_a_batch_by_family_and_size_class():
+    from paper_1507_07548_amd.serve import SIZE_CLASSES, backend_key
+    small, medium = SIZE_CLASSES
+    assert backend_key("2cljq", 256) == "2cljq/s"
+    assert backend_key("2cljq", small - 1) == "2cljq/s" and backend_key("2cljq", small) == "2cljq/m"
+    assert backend_key("ionic", medium - 1) == "ionic/m" and backend_key("ionic", medium) == "ionic/l"
+    assert backend_key("lj", 8192) == "lj/l"
+
+
+class SharedDevice:
+    """Counts the fake families' chunks in flight on one device."""
+
+    def __init__(self, clock):
+        self.clock, self.members, self.peak = clock, [], 0
+
+    def add(self, be):
+        self.members.append(be)
+        orig = be.launch
+
+        def launch(k):
+            orig(k)
+            self.peak = max(self.peak, sum(not m.ready() for m in self.members))
+        be.launch = launch
+        return be
+
+
+def test_shortest_remaining_work_goes_first_when_launches_are_limited():
+    """With one family in flight at a time, a small request that arrives
+    while a large batch is running takes the device at the next chunk
+    boundary and completes long before the large one; the large one still
+    completes."""
+    clk = FakeClock()
+    dev = SharedDevice(clk)
+    big = dev.add(FakeBackend(clk, cost=1.0))
+    small = dev.add(FakeBackend(clk, cost=0.01))
+    srv = Server({"big": big, "small": small}, hbm_budget=10 ** 9, chunk_steps=100, clock=clk,
+                 sleep=clk.sleep, max_inflight=1)
+    res = {r.rid: r for r in srv.run([req(0, 0.0, n=4000, model="big", steps=500),
+                                      req(1, 0.5, n=100, model="small", steps=300)])}
+    assert dev.peak == 1
+    assert res[1].status == 0 and res[1].steps_done == 300
+    assert 1.0 <= res[1].finished < 1.1            # waited for one large chunk only
+    assert res[0].status == 0 and res[0].steps_done == 500 and res[0].finished >= 5.0
+
+
+def test_launch_order_counts_the_whole_batch_cost():
+    """A family whose nearest request is short but whose batch is expensive
+    per step waits behind a family that is cheaper to finish."""
+    clk = FakeClock()
+    dev = SharedDevice(clk)
+    a = dev.add(FakeBackend(clk, max_slots=4, cost=0.1))
+    b = dev.add(FakeBackend(clk, max_slots=4, cost=0.1))
+    order = []
+    for name, be in (("a", a), ("b", b)):
+        inner = be.launch
+
+        def launch(k, name=name, inner=inner):
+            order.append(name)
+            inner(k)
+        be.launch = launch
+    # a: nearest request 200 steps, three n=1000 systems per step (cost 2 x 3e6 = 6e6)
+    # b: nearest request 400 steps, one n=500 system (cost 4 x 2.5e5 = 1e6)
+    reqs = [req(0, 0.0, n=1000, model="a", steps=200), req(1, 0.0, n=1000, model="a", steps=900),
+            req(2, 0.0, n=1000, model="a", steps=900), req(3, 0.0, n=500, model="b", steps=400)]
+    srv = Server({"a": a, "b": b}, hbm_budget=10 ** 9, chunk_steps=100, clock=clk, sleep=clk.sleep,
+                 max_inflight=1)
+    res = {r.rid: r for r in srv.run(reqs)}
+    assert order[:4] == ["b"] * 4 and dev.peak == 1
+    assert res[3].finished < res[0].finished
+    assert all(r.status == 0 for r in res.values())
+
+
+def test_max_inflight_must_be_positive():
+    with pytest.raises(ValueError):
+        Server({}, hbm_budget=1, max_inflight=0)
