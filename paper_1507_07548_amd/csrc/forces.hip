@@ -481,6 +481,10 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     lin_model.c12 = s_tab.c12[0][0];
     lin_model.K = kprod<Real>(s_tab.mqd[0][0], s_tab.mqd[0][0], E.inv_ke);
   }
+  // one species, centre cut-off: every listed pair counts, with the same
+  // number of site pairs, so the item's pair counters follow from the list
+  // length (no per-pair counting)
+  constexpr bool COUNT_ALL = ONE && !SITE;
   // 2.-3. the diagonal-major list, one pair per lane, chunks dealt to waves
   double a_ulj = 0, a_uel = 0, a_us = 0, a_uss = 0;
   double a_jq[3] = {0, 0, 0};
@@ -548,8 +552,10 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
       a_uel += (double)acc.uel;
       a_uss += (double)acc.uss;
       a_us -= (double)(Rx * Fi[0] + Ry * Fi[1] + Rz * Fi[2]);
-      a_np += (!SITE || ns > 0) ? 1 : 0;
-      a_ns += ns;
+      if constexpr (!COUNT_ALL) {
+        a_np += (!SITE || ns > 0) ? 1 : 0;
+        a_ns += ns;
+      }
       if constexpr (HF) {
         // pair part of the heat flux: u (v_i + v_j)/2 + R (F.(v_i + v_j) +
         // tau_i.w_i - tau_j.w_j)/2
@@ -639,6 +645,8 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
       double t = u.f.sums[0][lane];
 #pragma unroll
       for (int w = 1; w < NW; ++w) t += u.f.sums[w][lane];
+      if (COUNT_ALL && lane == 4) t = (double)total;
+      if (COUNT_ALL && lane == 5) t = (double)total * (double)s_tab.nsite[0][0];
       sd.bsum[(size_t)it.local * kNumBlockSums + lane] = t;
     }
   }

@@ -673,18 +673,21 @@ __device__ __forceinline__ void eval_linear_pair(const Real* ri, const Real* rj,
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const Real r2 = R2 + (Real(2) * Rd[k] + dd[k]);
-    const Real rR = R2 + Rd[k];
+    const Real rR = R2 + Rd[k];                                   // r . R
     const Real ir2 = rcp_(r2);
     const Real ir6 = ir2 * ir2 * ir2;
     const Real t6 = M.c6 * ir6;
     const Real t12 = M.c12 * ir6 * ir6;
-    dur[k] = (Real(6) * t6 - Real(12) * t12) * ir2;             // u'/r
-    const Real d2u = (Real(156) * t12 - Real(42) * t6) * ir2;   // u''
+    dur[k] = (Real(6) * t6 - Real(12) * t12) * ir2;               // u'/r
+    // (u'' - u'/r) (r.R)^2 / r^2 = (168 t12 - 48 t6) (r.R / r^2)^2;
+    // the (u'/r) R^2 part of every site pair is added once below
+    const Real p = rR * ir2;
     ulj += t12 - t6;
-    uss += (d2u - dur[k]) * (rR * rR * ir2) + dur[k] * R2;
+    uss += (Real(168) * t12 - Real(48) * t6) * (p * p);
   }
   const Real Em = dur[0] - dur[1], Sm = dur[0] + dur[1];
   const Real Ep = dur[2] - dur[3], Sp = dur[2] + dur[3];
+  uss += (Sm + Sp) * R2;
 
   const Real ir = rsq_(R2);
   const Real ca = (Rx * ei[0] + Ry * ei[1] + Rz * ei[2]) * ir;
