@@ -300,20 +300,24 @@ CASES = {
     # lone systems of the serving mix, advanced by graph replay (FP32)
     "lone_2cljq_256": lambda I: I.quadrupolar_fluid(n=256, density=0.6),
     "lone_2cljq_1000": lambda I: I.quadrupolar_fluid(n=1000, density=0.6),
+    "lone_2cljq_2000": lambda I: I.quadrupolar_fluid(n=2000, density=0.6),
     "lone_2cljq_4000": lambda I: I.quadrupolar_fluid(n=4000, density=0.6),
     "lone_2cljq_8192": lambda I: I.quadrupolar_fluid(n=8192, density=0.6),
     "lone_ionic_1000": lambda I: I.ionic_solution(),
 }
 
 
-def run_case(name, K, W):
-    """One lone system advanced K steps by graph replay; prints its step time."""
+def run_case(name, K, W, shape=None):
+    """One lone system advanced K steps by graph replay; prints its step time
+    (with `shape` = (wave_rows, j_chunk): that tile shape for its size)."""
     import torch
 
     from paper_1507_07548_amd import inputs, ms2
     s = CASES[name](inputs)
     s.md.n_steps = W + 2 * K + 10
     ctx = ms2.Context(s.species)
+    if shape:
+        ctx.set_tile_config(s.n, ms2.FP32, shape[0], shape[1], mode=1)
     b = ms2.Batch(ctx, 1)
     slot = b.admit(s, ms2.FP32)
     b.step(max(W, 1), graph=True)
@@ -325,10 +329,11 @@ def run_case(name, K, W):
     t1 = time.perf_counter()
     out = b.sample(slot, state=False)
     assert out["status"] == 0
+    used = list(ctx.tile_config(s.n, ms2.FP32, mode=1))
     b.close()
     ctx.close()
-    print(json.dumps({"case": name, "molecules": s.n, "steps": K, "ms_per_step": (t1 - t0) / K * 1e3}),
-          flush=True)
+    print(json.dumps({"case": name, "molecules": s.n, "steps": K, "ms_per_step": (t1 - t0) / K * 1e3,
+                      "tile_shape": used}), flush=True)
 
 
 def main():
@@ -371,7 +376,7 @@ def main():
 
     K, W = args.steps, args.warmup
     if args.case:
-        run_case(args.case, K, W)
+        run_case(args.case, K, W, tuple(int(x) for x in args.tile_shape.split(",")) if args.tile_shape else None)
         return
     # the host baseline runs first: its worker processes start before this
     # process touches the GPU

@@ -152,9 +152,9 @@ ms2_status ms2_forces(ms2_ctx* ctx, const ms2_params* h_params, int32_t n_mol,
 /* ms2_forces for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Same arguments, outputs, errors and device-side species check as
- * ms2_forces, and the same result bit for bit as ms2_forces with its default
- * tile shape (symmetric 64 x 64 tile pairs; this call always takes that
- * shape).  It calls no hipMalloc/hipFree and allocates nothing: its scratch
+ * ms2_forces, and the same result bit for bit as ms2_forces with its untuned
+ * default tile shape (symmetric 64 x 64 tile pairs, 1, 2 or 4 items per
+ * tile pair by the system size; this call always takes that shape).  It calls no hipMalloc/hipFree and allocates nothing: its scratch
  * (site records, pair partials, block sums, work items; under 16 MiB) is a
  * static device array that each GPU the library runs on holds until the
  * process ends.  Limit: 2 <= n_mol <= MS2_NOALLOC_MAX_MOL, otherwise
@@ -343,8 +343,11 @@ ms2_status ms2_slot_status(ms2_batch* batch, int32_t slot, int64_t* steps_done,
 
 /* Pair-kernel tile shape for n molecules: wave_rows waves of 64 molecules i
  * per block, j_chunk molecules j per work item (row-owned: every pair is
- * evaluated from both sides), or wave_rows = 0 with j_chunk = 64: symmetric
- * items of 64 x 64 tile pairs, every pair evaluated once.  The shape depends only on
+ * evaluated from both sides), or wave_rows = 0: symmetric items of 64 x 64
+ * tile pairs, every pair evaluated once, with j_chunk = 64 / S for S = 1, 2
+ * or 4 items per tile pair, each taking every S-th 64-pair chunk of the
+ * pair's list (S > 1 puts more workgroups in flight for small systems, at
+ * the price of S cut-off tests per tile pair).  The shape depends only on
  * the context's model class, the precision, the launch mode (0: one system
  * per launch, 1: batched) and the size bucket floor(log2 n) -- never on which
  * other systems share a launch.  Until ms2_autotune or ms2_set_tile_config

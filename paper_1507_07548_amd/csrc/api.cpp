@@ -314,18 +314,29 @@ int size_bucket(int n) {
   return b;  // floor(log2 n)
 }
 
+TileCfg default_sym_shape(int n, int cus) {
+  const int nt = (n + 63) / 64, items = nt * (nt + 1) / 2;
+  int S = 1;
+  while (S < kMaxSplits && items * S < cus) S *= 2;
+  TileCfg c;
+  c.waves = 0;
+  c.jchunk = 64 / S;
+  return c;
+}
+
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
   auto it = ctx->tuned.find(std::make_tuple(mode, precision, size_bucket(n)));
   if (it != ctx->tuned.end()) return it->second;
   // untuned: symmetric tile pairs, every pair evaluated once, in both launch
   // modes (one system per launch as well: 1.2-2.5x faster than row-owned
-  // items from N = 500 to 8192 for the LJ, 2CLJQ and ionic models)
+  // items from N = 500 to 8192 for the LJ, 2CLJQ and ionic models); small
+  // systems deal each tile pair to 2 or 4 items so that they fill the
+  // device (a lone 2CLJQ system, N = 256 / 1000: 42 -> 36 / 50 -> 43 us per
+  // MD step; water + ions, N = 1000: 134 -> 112 us).  The shape depends on n
+  // alone, so a system gets the same items alone and in a mix.
   (void)mode;
-  (void)n;
-  TileCfg c;
-  c.waves = 0;
-  c.jchunk = 64;
-  return c;
+  (void)precision;
+  return default_sym_shape(n, ctx->cus);
 }
 
 static bool single_species_form(const ms2_ctx* ctx) {
@@ -361,22 +372,25 @@ int pair_form(const ms2_ctx* ctx) {
 }
 
 int build_items(int n, const TileCfg& c, int slot, std::vector<WorkItem>& out, int* jsplits) {
-  if (c.waves == 0) {  // symmetric: tile pairs (I, J >= I) of 64 molecules
-    const int nt = (n + 63) / 64;
+  if (c.waves == 0) {  // symmetric: tile pairs (I, J >= I) of 64 molecules, S items each
+    const int nt = (n + 63) / 64, S = sym_splits(c);
     int local = 0;
     for (int I = 0; I < nt; ++I)
-      for (int J = I; J < nt; ++J) {
-        WorkItem w{};
-        w.slot = slot;
-        w.i0 = 64 * I;
-        w.j0 = 64 * J;
-        w.j1 = std::min(n, 64 * J + 64);
-        w.part = J;
-        w.part_j = I;
-        w.local = local++;
-        out.push_back(w);
-      }
-    *jsplits = nt;
+      for (int J = I; J < nt; ++J)
+        for (int sp = 0; sp < S; ++sp) {
+          // partial index k S + sp of tile index k: each written by one item
+          WorkItem w{};
+          w.slot = slot;
+          w.i0 = 64 * I;
+          w.j0 = 64 * J;
+          w.j1 = std::min(n, 64 * J + 64);
+          w.part = J * S + sp;
+          w.part_j = I * S + sp;
+          w.local = local++;
+          w.split = S > 1 ? sp + 256 * S : 0;
+          out.push_back(w);
+        }
+    *jsplits = nt * S;
     return local;
   }
   const int it = 64 * c.waves;
@@ -424,7 +438,7 @@ static ms2_status single_setup(ms2_ctx* ctx, const ms2_params* p, int n, const i
   MS2_HIP(hipSetDevice(ctx->device));
   const int npad = (n + 63) & ~63;
   TileCfg cfg = tile_config(ctx, 0, p->precision, n);
-  if (p->cutoff_mode == MS2_CUT_SITE) {   // the site-site cut-off runs on symmetric items only
+  if (p->cutoff_mode == MS2_CUT_SITE && cfg.waves != 0) {   // the site-site cut-off runs on symmetric items only
     cfg.waves = 0;
     cfg.jchunk = 64;
   }
@@ -538,6 +552,7 @@ ms2_status ms2_create(ms2_ctx** out, const ms2_species* h_species, int32_t n_spe
     return set_error(MS2_EINVAL, "site counts exceed every compiled model class");
   }
   hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipMalloc(&c->d_tab, sizeof(SpeciesTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, &c->tab, sizeof(SpeciesTable), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
@@ -657,8 +672,8 @@ ms2_status ms2_set_tile_config(ms2_ctx* ctx, int32_t mode, int32_t n_mol, int32_
   if (!(wave_rows == 0 || wave_rows == 1 || (wave_rows == 4 && ctx->cls <= 3)))
     return set_error(MS2_EINVAL,
                      "wave_rows must be 0 (symmetric), 1, or 4 (first four model classes only)");
-  if (wave_rows == 0 && j_chunk != 64)
-    return set_error(MS2_EINVAL, "symmetric tiles use j_chunk = 64");
+  if (wave_rows == 0 && j_chunk != 64 && j_chunk != 32 && j_chunk != 16)
+    return set_error(MS2_EINVAL, "symmetric tiles use j_chunk = 64, 32 or 16 (1, 2 or 4 items per tile pair)");
   if (wave_rows > 0 && (j_chunk < 64 * wave_rows || j_chunk % (64 * wave_rows) != 0))
     return set_error(MS2_EINVAL, "j_chunk must be a positive multiple of 64 * wave_rows");
   TileCfg c;

@@ -115,10 +115,10 @@ extern "C" ms2_status ms2_autotune(ms2_ctx* ctx, int32_t precision, int32_t n_lo
     make_synthetic(ctx, n, precision, syn);
     for (int mode = 0; mode <= 1; ++mode) {
       std::vector<TileCfg> cand;
-      {
-        TileCfg sym;   // symmetric 64 x 64 tile pairs
+      for (int S = 1; S <= kMaxSplits; S *= 2) {
+        TileCfg sym;   // symmetric 64 x 64 tile pairs, S items per tile pair
         sym.waves = 0;
-        sym.jchunk = 64;
+        sym.jchunk = 64 / S;
         cand.push_back(sym);
       }
       const int wmax = (mode == 1 && ctx->cls <= 3) ? 4 : 1;

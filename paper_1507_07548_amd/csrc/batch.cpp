@@ -227,16 +227,16 @@ ms2_status shape_of(ms2_ctx* ctx, const ms2_system* sys, int mode, SlotShape& s)
   s.mode = mode;
   TileCfg cfg = tile_config(ctx, mode, s.precision, s.n);
   s.site_cut = sys->params.cutoff_mode == MS2_CUT_SITE ? 1 : 0;
-  if (sys->heat_flux || s.site_cut) {   // both are evaluated on symmetric items only
+  if ((sys->heat_flux || s.site_cut) && cfg.waves != 0) {   // both are evaluated on symmetric items only
     cfg.waves = 0;
     cfg.jchunk = 64;
   }
   s.waves = cfg.waves;
   s.jchunk = cfg.jchunk;   // frozen at admission: the slot's buffers are sized for it
-  if (cfg.waves == 0) {    // symmetric tile pairs
-    const int nt = (s.n + 63) / 64;
-    s.jsplits = nt;
-    s.nitems = nt * (nt + 1) / 2;
+  if (cfg.waves == 0) {    // symmetric tile pairs, S items each
+    const int nt = (s.n + 63) / 64, S = sym_splits(cfg);
+    s.jsplits = nt * S;
+    s.nitems = nt * (nt + 1) / 2 * S;
   } else {
     s.jsplits = (s.n + cfg.jchunk - 1) / cfg.jchunk;
     s.nitems = ((s.n + 64 * cfg.waves - 1) / (64 * cfg.waves)) * s.jsplits;

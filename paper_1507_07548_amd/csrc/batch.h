@@ -21,8 +21,14 @@ struct DevBuf {
 
 struct TileCfg {
   int waves = 1;    // waves per block (64 i molecules each); 0 = symmetric tile pairs
-  int jchunk = 64;  // j molecules per work item
+  int jchunk = 64;  // j molecules per work item; symmetric: 64 / S, S items per tile pair
 };
+// items per symmetric tile pair (1, 2 or 4); 1 for row-owned shapes
+inline int sym_splits(const TileCfg& c) { return c.waves == 0 && c.jchunk > 0 ? 64 / c.jchunk : 1; }
+// the untuned symmetric shape for n molecules on a device of `cus` compute
+// units: the fewest items per tile pair (1, 2, 4) that give the system at
+// least one item per compute unit
+TileCfg default_sym_shape(int n, int cus);
 
 struct CachedItems {
   DevBuf buf;
@@ -48,6 +54,7 @@ ms2_status hip_status(hipError_t e, const char* where);
 struct ms2_ctx {
   int device = 0;
   int cls = 0;
+  int cus = 256;           // compute units of the device (untuned tile shapes)
   ms2::SpeciesTable tab;
   ms2::SpeciesTable* d_tab = nullptr;
   int* d_err = nullptr;    // device error word of the single-system entry points

@@ -493,7 +493,10 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   Real(*stage)[TJ] = u.t.stage[wv];
   int* list = s_list[wv];
   unsigned char(*keep)[TJ] = u.t.er[wv];
-  for (int q = wv * TJ; q < total; q += NW * TJ) {
+  // this item's share of the list: chunks s, s + S, ... of the tile pair's
+  // ceil(total / 64), dealt to the four waves in turn
+  const int n_split = split_count(it.split), i_split = split_index(it.split);
+  for (int q = (wv + NW * i_split) * TJ; q < total; q += NW * n_split * TJ) {
     const bool valid = q + lane < total;
     const int qend = min(q + TJ, total);
     // the chunk's diagonals (wave-uniform): from the first one ending after
@@ -645,8 +648,9 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
       double t = u.f.sums[0][lane];
 #pragma unroll
       for (int w = 1; w < NW; ++w) t += u.f.sums[w][lane];
-      if (COUNT_ALL && lane == 4) t = (double)total;
-      if (COUNT_ALL && lane == 5) t = (double)total * (double)s_tab.nsite[0][0];
+      // the first of a tile pair's items counts its whole list
+      if (COUNT_ALL && lane == 4) t = i_split == 0 ? (double)total : 0.0;
+      if (COUNT_ALL && lane == 5) t = i_split == 0 ? (double)total * (double)s_tab.nsite[0][0] : 0.0;
       sd.bsum[(size_t)it.local * kNumBlockSums + lane] = t;
     }
   }

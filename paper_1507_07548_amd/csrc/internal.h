@@ -137,10 +137,15 @@ __host__ __device__ inline bool species_ok(int s, int nsp) { return (unsigned)s 
 // A pair-kernel work item: molecules [i0, i0 + 64 W) of a slot against
 // j in [j0, j1); `part` selects the per-molecule partial buffer of the i
 // side, `part_j` that of the j side (symmetric items), `local` the item's
-// block-sum row within its slot.
+// block-sum row within its slot.  `split` (symmetric items): a tile pair's
+// pair list may be dealt to S items, this one taking its chunks s, s + S,
+// ...; split = s + 256 S, and 0 stands for s = 0, S = 1.
 struct WorkItem {
-  int slot, i0, j0, j1, part, local, part_j, pad;
+  int slot, i0, j0, j1, part, local, part_j, split;
 };
+__host__ __device__ inline int split_count(int split) { return split >> 8 > 1 ? split >> 8 : 1; }
+__host__ __device__ inline int split_index(int split) { return split & 255; }
+constexpr int kMaxSplits = 4;   // symmetric items per tile pair
 
 constexpr int kNumMoments = 11;   // N, X, X^2, X^3, Y, XY, X^2Y, Y^2, XY^2, Z, XZ
 constexpr int kMdThreads = 1024;  // one block per slot for the per-system passes of the MD step

@@ -610,7 +610,8 @@ __global__ __launch_bounds__(64 * W) void rdf_kernel(const WorkItem* __restrict_
   const WorkItem it = items[item_base + blockIdx.x];
   const SlotDev& sd = slots[it.slot];
   const MDDev& m = md[it.slot];
-  if (!m.rdf_due) return;
+  // a tile pair dealt to several symmetric items is histogrammed by the first
+  if (!m.rdf_due || split_index(it.split) != 0) return;
   const SysParams& P = prm[it.slot];
   const int tid = threadIdx.x, n = sd.n, ld = sd.com_ld, nsp = tab->nsp;
   const int bins = m.rdf_bins, T = tab->n_lj_types;

@@ -15,9 +15,10 @@
 // address once per device, with that device current, and every launch takes
 // that address.
 //
-// The work items are the symmetric 64 x 64 tile pairs of ms2_forces' default
-// shape, written by a small kernel in the order the host list uses, so the
-// result equals ms2_forces with that shape bit for bit.  Every scratch entry
+// The work items are the symmetric 64 x 64 tile pairs of ms2_forces' untuned
+// default shape (1, 2 or 4 items per tile pair by the system's size), written
+// by a small kernel in the order the host list uses, so the result equals
+// ms2_forces with that shape bit for bit.  Every scratch entry
 // a kernel reads was written earlier in the same call (site records and
 // partials of every molecule and tile index, block sums of every item), so
 // nothing is cleared between calls.  All calls on one GPU share the array:
@@ -84,26 +85,28 @@ unsigned char* scratch_on(int device) {
   return it == g_scratch_ptr.end() ? nullptr : it->second;
 }
 
-// Symmetric tile pairs (I, J >= I) of ceil(n / 64) tiles, row-major in I:
-// thread I writes row I, whose first item index is the number of pairs in
-// rows 0 .. I-1, sum_{r < I} (nt - r).  Same items, same order as the host
-// list of the default shape.
-__global__ __launch_bounds__(64) void noalloc_items_kernel(WorkItem* __restrict__ items, int n) {
+// Symmetric tile pairs (I, J >= I) of ceil(n / 64) tiles, row-major in I,
+// S items per tile pair: thread I writes row I, whose first tile pair is
+// the number of pairs in rows 0 .. I-1, sum_{r < I} (nt - r).  Same items,
+// same order as the host list of the default shape.
+__global__ __launch_bounds__(64) void noalloc_items_kernel(WorkItem* __restrict__ items, int n, int S) {
   const int nt = (n + 63) / 64;
   const int I = threadIdx.x;
   if (I >= nt) return;
   int k = I * nt - I * (I - 1) / 2;
   for (int J = I; J < nt; ++J, ++k) {
-    WorkItem w;
-    w.slot = 0;
-    w.i0 = 64 * I;
-    w.j0 = 64 * J;
-    w.j1 = min(n, 64 * J + 64);
-    w.part = J;
-    w.local = k;
-    w.part_j = I;
-    w.pad = 0;
-    items[k] = w;
+    for (int sp = 0; sp < S; ++sp) {
+      WorkItem w;
+      w.slot = 0;
+      w.i0 = 64 * I;
+      w.j0 = 64 * J;
+      w.j1 = min(n, 64 * J + 64);
+      w.part = J * S + sp;
+      w.local = k * S + sp;
+      w.part_j = I * S + sp;
+      w.split = S > 1 ? sp + 256 * S : 0;
+      items[k * S + sp] = w;
+    }
   }
 }
 
@@ -143,7 +146,11 @@ extern "C" ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_param
   if (!base) return set_error(MS2_EDEVICE, "no-allocation scratch was not attached on this device");
 
   const int n = n_mol, npad = (n + 63) & ~63, nt = npad / 64;
-  const int nitems = nt * (nt + 1) / 2;
+  // the default symmetric shape of ms2_forces (S items per tile pair), within
+  // the scratch's item and partial capacity
+  int S = sym_splits(default_sym_shape(n, ctx->cus));
+  while (S > 1 && ((size_t)nt * (nt + 1) / 2 * S > (size_t)kNaItems || nt * S > kNaTiles)) S /= 2;
+  const int nitems = nt * (nt + 1) / 2 * S;
   const int nk = h_params->elec == MS2_ELEC_EWALD ? kvec_count(h_params->kmax2) : 0;
   RingSlot* r = nullptr;
   s = ring_acquire(ctx, &r);
@@ -153,7 +160,7 @@ extern "C" ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_param
   std::memset(&d, 0, sizeof(d));
   d.n = n;
   d.npad = npad;
-  d.jsplits = nt;
+  d.jsplits = nt * S;
   d.nitems = nitems;
   d.active = 1;
   d.symmetric = 1;
@@ -179,7 +186,7 @@ extern "C" ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_param
   } while (0)
   MS2_NA_HIP(hipMemcpyAsync(r->d_slot, r->h_slot, sizeof(SlotDev), hipMemcpyHostToDevice, st));
   MS2_NA_HIP(hipMemcpyAsync(r->d_prm, r->h_prm, sizeof(SysParams), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(noalloc_items_kernel, dim3(1), dim3(64), 0, st, items, n);
+  hipLaunchKernelGGL(noalloc_items_kernel, dim3(1), dim3(64), 0, st, items, n, S);
   MS2_NA_HIP(hipGetLastError());
   MS2_NA_HIP(launch_site_frame(ctx->cls, h_params->precision, r->d_slot, r->d_prm, ctx->d_tab, 1, n, st));
   MS2_NA_HIP(launch_pair(ctx->cls, h_params->precision, 0, false, h_params->cutoff_mode == MS2_CUT_SITE,

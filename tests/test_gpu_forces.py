@@ -308,7 +308,8 @@ def test_a_bad_device_species_index_poisons_the_reciprocal_sums():
 # --------------------------------------------------------------------------
 # tile shapes: the work decomposition never changes the result beyond rounding
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("waves,jchunk", [(0, 64), (1, 64), (1, 192), (1, 1024), (4, 256), (4, 2048)])
+@pytest.mark.parametrize("waves,jchunk", [(0, 64), (0, 32), (0, 16), (1, 64), (1, 192), (1, 1024), (4, 256),
+                                          (4, 2048)])
 def test_tile_shape_does_not_change_the_result(waves, jchunk):
     s = I.jittered(I.quadrupolar_fluid(n=1100, density=0.6), 0.1, seed=3)
     ctx = ms2.Context(s.species)
@@ -364,7 +365,7 @@ def test_autotuner_picks_a_valid_shape_for_every_bucket():
     for n in (300, 600, 1300):
         for mode in (0, 1):
             w, j = ctx.tile_config(n, ms2.FP32, mode=mode)
-            assert (w == 0 and j == 64) or (w in (1, 4) and j % (64 * w) == 0)
+            assert (w == 0 and j in (64, 32, 16)) or (w in (1, 4) and j % (64 * w) == 0)
     f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, ctx=ctx, label="after autotune")
     assert ef < 1e-5
 
@@ -441,3 +442,75 @@ def test_two_centre_forms_match_the_oracle(name, n):
             check_sums(su, so, 1e-11, 1e-12)
         else:
             assert energy_error(su, so) < 1e-6      # jittered lattice starts (coherent rounding)
+
+
+# --------------------------------------------------------------------------
+# split symmetric items: S = 64 / j_chunk items per tile pair, each taking
+# every S-th chunk of the pair list, with partials and block sums of its own
+# --------------------------------------------------------------------------
+def split_cases():
+    # the site-site cut-off needs rc + 2 d_max < L / 2
+    site = I.jittered(I.quadrupolar_fluid(n=700, density=0.6, rc_frac=0.4), 0.1, seed=21)
+    site.params.cutoff_mode = I.CUT_SITE
+    return {
+        "2cljq": lambda: I.jittered(I.quadrupolar_fluid(n=1000, density=0.6), 0.1, seed=22),
+        "water_ions": lambda: I.ionic_solution(),
+        "offset_multipoles": lambda: small_system([offset_multipoles(), I.stockmayer()], 300,
+                                                  1.4 * 300 ** (1 / 3) + 2.5, 0.45 * (1.4 * 300 ** (1 / 3) + 2.5),
+                                                  seed=24, elec=I.ELEC_RF, eps_rf=25.0),
+        "site_cut_2cljq": lambda: site,
+    }
+
+
+@pytest.mark.parametrize("jchunk", [32, 16])
+@pytest.mark.parametrize("name", ["2cljq", "water_ions", "offset_multipoles", "site_cut_2cljq"])
+def test_split_items_fp64_parity(name, jchunk):
+    s = split_cases()[name]()
+    ctx = ms2.Context(s.species)
+    ctx.set_tile_config(s.n, ms2.FP64, 0, jchunk, mode=0)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP64, ctx=ctx, label=f"{name} split {64 // jchunk}")
+    assert ef < 1e-11 and et < 1e-11, (ef, et)
+    check_sums(su, so, 1e-11, 1e-12)
+
+
+@pytest.mark.parametrize("jchunk", [32, 16])
+def test_split_items_fp32_linear_form(jchunk):
+    """The FP32 linear two-centre form with split items: the oracle's counters
+    exactly and the FP32 bounds; against one item per tile pair, the same
+    per-pair values summed in another order (energies to FP64 rounding)."""
+    s = I.jittered(I.quadrupolar_fluid(n=1000, density=0.6), 0.1, seed=23)
+    ctx = ms2.Context(s.species)
+    ctx.set_tile_config(s.n, ms2.FP32, 0, jchunk, mode=0)
+    f, t, su, fo, to, so, ef, et = compare(s, ms2.FP32, ctx=ctx, label=f"2cljq fp32 split {64 // jchunk}")
+    assert ef < 1e-5 and et < 1e-5
+    assert energy_error(su, so) < 5e-8
+    f1, t1, s1 = ms2.evaluate(ms2.Context(s.species), s, ms2.FP32)
+    assert np.array_equal(su[[NPAIR, NSITE]], s1[[NPAIR, NSITE]])
+    for k in U_SLOTS:
+        assert abs(su[k] - s1[k]) <= 1e-13 * np.abs(s1[U_SLOTS]).sum(), (k, su[k], s1[k])
+    rms = np.sqrt((f1 ** 2).sum(1).mean())
+    assert np.abs(f - f1).max() <= 1e-6 * rms
+
+
+def test_split_items_in_a_batch_match_the_lone_system():
+    """A batch whose size buckets use split items: every system bit for bit
+    the same as when it is alone in a batch with the same shapes."""
+    systems = [I.quadrupolar_fluid(n=n, density=0.5, seed=30 + k) for k, n in enumerate((300, 700, 1000))]
+    ctx = ms2.Context(systems[0].species)
+    for s in systems:
+        ctx.set_tile_config(s.n, ms2.FP32, 0, 32, mode=1)
+    mixed = ms2.Batch(ctx, 4)
+    slots = [mixed.admit(s, ms2.FP32) for s in systems]
+    mixed.step(20, graph=True)
+    for s, slot in zip(systems, slots):
+        alone = ms2.Batch(ctx, 1)
+        a_slot = alone.admit(s, ms2.FP32)
+        alone.step(20, graph=True)
+        a = alone.sample(a_slot, state=True)
+        m = mixed.sample(slot, state=True)
+        say(f"[gpu] split batch n={s.n}: status {m['status']} {a['status']}")
+        assert m["status"] == 0 and a["status"] == 0
+        for key in ("com", "quat", "moments"):
+            assert np.array_equal(np.asarray(m[key]), np.asarray(a[key])), key
+        alone.close()
+    mixed.close()

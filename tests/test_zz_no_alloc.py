@@ -40,7 +40,9 @@ def run_pair(systems, precision):
     then ms2_forces on each; returns the four output triples."""
     ctx = ms2.Context(systems[0].species)
     for s in systems:
-        assert ctx.tile_config(s.n, precision, mode=0) == (0, 64)   # the default shape
+        # the untuned default: symmetric items, 1, 2 or 4 per tile pair by size
+        # (on a 256-CU device: N = 4096 one, N = 1000 two)
+        assert ctx.tile_config(s.n, precision, mode=0)[0] == 0
     devs = [ms2.DeviceSystem(s) for s in systems]
     p = [ms2.params_struct(s.params, precision) for s in systems]
     # a first launch loads the kernels' code objects (runtime memory, not
@@ -75,6 +77,8 @@ def run_pair(systems, precision):
 def test_noalloc_equals_forces_two_calls_second_smaller(precision):
     big = I.jittered(I.quadrupolar_fluid(n=ms2.NOALLOC_MAX_MOL, density=0.45), 0.1, seed=41)
     small = I.jittered(I.quadrupolar_fluid(n=1000, density=0.6), 0.1, seed=42)
+    shapes = {s.n: ms2.Context(s.species).tile_config(s.n, precision, mode=0) for s in (big, small)}
+    say(f"  default shapes {shapes}")
     got, ref, free0, free1 = run_pair([big, small], precision)
     for (fa, ta, sa), (fb, tb, sb) in zip(got, ref):
         assert np.array_equal(fa, fb) and np.array_equal(ta, tb) and np.array_equal(sa, sb)
