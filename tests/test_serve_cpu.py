@@ -178,12 +178,15 @@ def test_nearest_rank_percentiles():
 
 
 def test_requests_join_a_batch_by_family_and_size_class():
-    from paper_1507_07548_amd.serve import SIZE_CLASSES, backend_key
-    small, medium = SIZE_CLASSES
-    assert backend_key("2cljq", 256) == "2cljq/s"
-    assert backend_key("2cljq", small - 1) == "2cljq/s" and backend_key("2cljq", small) == "2cljq/m"
-    assert backend_key("ionic", medium - 1) == "ionic/m" and backend_key("ionic", medium) == "ionic/l"
-    assert backend_key("lj", 8192) == "lj/l"
+    from paper_1507_07548_amd.serve import SIZE_CLASSES, backend_key, size_class
+    small, large = SIZE_CLASSES[0], SIZE_CLASSES[-1]
+    last = len(SIZE_CLASSES)
+    assert backend_key("2cljq", 256) == "2cljq/0"
+    assert backend_key("2cljq", small - 1) == "2cljq/0" and backend_key("2cljq", small) == "2cljq/1"
+    assert backend_key("ionic", large - 1) == f"ionic/{last - 1}" and backend_key("ionic", large) == f"ionic/{last}"
+    assert backend_key("lj", 8192) == f"lj/{last}"
+    assert [size_class(n, (1000, 2000, 4000)) for n in (999, 1000, 1999, 2000, 3999, 4000)] == [0, 1, 1, 2, 2, 3]
+    assert backend_key("lj", 3000, classes=(1000, 2000, 4000)) == "lj/2"
 
 
 class SharedDevice:
