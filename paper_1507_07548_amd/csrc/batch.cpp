@@ -29,6 +29,11 @@ hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int ns
 hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
                          int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
                          int max_kchunks, hipStream_t st);
+hipError_t launch_kspace_partials(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
+                                  int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
+                                  int max_kchunks, hipStream_t st);
+hipError_t launch_reduce_pair_kspace(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
+                                     hipStream_t st);
 hipError_t launch_md_wrap(MDDev* md, const SysParams* prm, int slot, int n, hipStream_t st);
 hipError_t launch_md_init(SlotDev* slots, MDDev* md, const SpeciesTable* tab, int slot,
                           hipStream_t st);
@@ -360,10 +365,15 @@ ms2_status enqueue_forces(ms2_batch* b, hipStream_t st, int timed_step) {
     MS2_HIP(launch_pair(ctx->cls, g.precision, g.waves, g.heat_flux, g.site_cut, pair_form(ctx), di, g.begin,
                         g.end - g.begin, ds, dp, ctx->d_tab, st));
   if (timed_step >= 0) MS2_HIP(hipEventRecord(b->ev_end[timed_step], st));
-  MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
-  if (b->any_ewald)
-    MS2_HIP(launch_kspace(ds, dp, ctx->d_tab, b->max_slots, b->max_kblocks, b->max_mchunks,
-                          b->max_mtiles, b->max_kchunks, st));
+  if (b->any_ewald) {
+    // reciprocal partials first; one reduction then adds pair and reciprocal
+    // parts (the same bits as the pair reduction followed by the reciprocal ones)
+    MS2_HIP(launch_kspace_partials(ds, dp, ctx->d_tab, b->max_slots, b->max_kblocks, b->max_mchunks,
+                                   b->max_mtiles, b->max_kchunks, st));
+    MS2_HIP(launch_reduce_pair_kspace(ds, dp, b->max_slots, b->max_n, st));
+  } else {
+    MS2_HIP(launch_reduce_pair(ds, dp, b->max_slots, b->max_n, st));
+  }
   return MS2_OK;
 }
 

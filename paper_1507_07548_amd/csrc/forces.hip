@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "kspace_sums.h"
 #include "pair_math.h"
 #include "quat.h"
 #include "site_frame.h"
@@ -669,7 +670,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
 // blocks, six runs of molecule blocks, one per force/torque component, so
 // that the largest systems' serial chains are one component long
 __device__ __forceinline__ void reduce_force_block(const SlotDev* __restrict__ slots,
-                                                   const SysParams* __restrict__ prm, int bx, int mb) {
+                                                   const SysParams* __restrict__ prm, int bx, int mb, bool with_k) {
   const SlotDev& sd = slots[blockIdx.y];
   if (!sd.active) return;
   const int c = bx / mb;
@@ -697,6 +698,9 @@ __device__ __forceinline__ void reduce_force_block(const SlotDev* __restrict__ s
     reduce(reinterpret_cast<const float*>(sd.pf) + (size_t)c * np + i);
   else
     reduce(reinterpret_cast<const double*>(sd.pf) + (size_t)c * np + i);
+  // the reciprocal part added to the stored pair sum, as its own reduction
+  // would add it
+  if (with_k && prm[blockIdx.y].elec == MS2_ELEC_EWALD) v = v + kspace_force_sum(sd, c, i);
   if (c < 3)
     sd.force[c * ld + i] = v;
   else
@@ -704,11 +708,13 @@ __device__ __forceinline__ void reduce_force_block(const SlotDev* __restrict__ s
 }
 
 __device__ __forceinline__ void reduce_sums_block(const SlotDev* __restrict__ slots,
-                                                  const SysParams* __restrict__ prm, int slot) {
-  // per-wave totals only (a few hundred bytes): the launch's force blocks
-  // share this kernel's static LDS size, so the sums keep it small
+                                                  const SysParams* __restrict__ prm, int slot, bool with_k) {
+  // per-wave totals and the reciprocal sums' trees (6 KB): the launch's
+  // force blocks share this kernel's static LDS size, so the sums keep it
+  // small
   __shared__ double s_red[4][kNumBlockSums];
   __shared__ int s_cnt[4][kMaxSp];
+  __shared__ double s_kd[256], s_ku[256], s_kw[256];
   const SlotDev& sd = slots[slot];
   if (!sd.active) return;
   const SysParams& P = prm[slot];
@@ -818,17 +824,25 @@ __device__ __forceinline__ void reduce_sums_block(const SlotDev* __restrict__ sl
       if (sd.err) *sd.err = 1;
     }
   }
+  if (with_k && P.elec == MS2_ELEC_EWALD) {
+    __syncthreads();
+    kspace_sums_block(sd, P, s_kd, s_ku, s_kw);
+  }
 }
 
 // Both reductions in one launch: grid (6 x molecule blocks + 1, slots); the
-// last block of each slot's row sums its work items' block sums.
+// last block of each slot's row sums its work items' block sums.  With
+// with_k, Ewald slots also get their reciprocal forces, torques and sums
+// (the structure factor and force partials must be complete), added after
+// the pair sums as the reciprocal reductions would add them: the same bits
+// in one launch instead of three.
 __global__ __launch_bounds__(256) void reduce_pair_kernel(const SlotDev* __restrict__ slots,
-                                                          const SysParams* __restrict__ prm) {
+                                                          const SysParams* __restrict__ prm, int with_k) {
   const int mb = (gridDim.x - 1) / 6;
   if ((int)blockIdx.x < 6 * mb)
-    reduce_force_block(slots, prm, blockIdx.x, mb);
+    reduce_force_block(slots, prm, blockIdx.x, mb, with_k != 0);
   else
-    reduce_sums_block(slots, prm, blockIdx.y);
+    reduce_sums_block(slots, prm, blockIdx.y, with_k != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,7 +951,14 @@ hipError_t launch_pair(int cls, int precision, int waves, bool heat_flux, bool s
 hipError_t launch_reduce_pair(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
                               hipStream_t st) {
   hipLaunchKernelGGL(reduce_pair_kernel, dim3(6 * ((max_n + 255) / 256) + 1, nslots), dim3(256), 0, st, slots,
-                     prm);
+                     prm, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_pair_kspace(const SlotDev* slots, const SysParams* prm, int nslots, int max_n,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(reduce_pair_kernel, dim3(6 * ((max_n + 255) / 256) + 1, nslots), dim3(256), 0, st, slots,
+                     prm, 1);
   return hipGetLastError();
 }
 

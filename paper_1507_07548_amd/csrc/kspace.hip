@@ -20,11 +20,11 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "kspace_sums.h"
 #include "quat.h"
 
 namespace ms2 {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.14159265358979323846264338328;
 
 __device__ __forceinline__ void quat_rot(const double* q, int ld, int i, double A[3][3]) {
@@ -305,8 +305,7 @@ __global__ __launch_bounds__(64) void kforce_kernel(const SlotDev* __restrict__ 
 
 // One thread per (component, molecule): the grid's x holds six runs of
 // molecule blocks, one per force/torque component; the chunk partials are
-// added in chunk order (the loads of four chunks issued before their
-// additions).
+// added in chunk order (kspace_force_sum).
 __global__ __launch_bounds__(256) void reduce_kforce_kernel(const SlotDev* __restrict__ slots,
                                                             const SysParams* __restrict__ prm) {
   const SlotDev& sd = slots[blockIdx.y];
@@ -315,20 +314,8 @@ __global__ __launch_bounds__(256) void reduce_kforce_kernel(const SlotDev* __res
   const int mb = gridDim.x / 6, c = blockIdx.x / mb;
   const int i = (blockIdx.x - c * mb) * 256 + threadIdx.x;
   if (i >= sd.n) return;
-  const int np = sd.npad, ld = sd.com_ld;
-  const double* fk = sd.fk + (size_t)c * np + i;
-  const size_t stride = (size_t)6 * np;
-  double v = 0.0;
-  int kc = 0;
-  for (; kc + 4 <= sd.kchunks; kc += 4) {
-    const double a = fk[kc * stride], b = fk[(kc + 1) * stride];
-    const double e = fk[(kc + 2) * stride], f = fk[(kc + 3) * stride];
-    v += a;
-    v += b;
-    v += e;
-    v += f;
-  }
-  for (; kc < sd.kchunks; ++kc) v += fk[kc * stride];
+  const int ld = sd.com_ld;
+  const double v = kspace_force_sum(sd, c, i);
   if (c < 3)
     sd.force[c * ld + i] += v;
   else
@@ -341,62 +328,28 @@ __global__ __launch_bounds__(256) void reduce_ksums_kernel(const SlotDev* __rest
   const SlotDev& sd = slots[blockIdx.x];
   const SysParams& P = prm[blockIdx.x];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
-  const int tid = threadIdx.x;
-  // sum_a d_a . F_a over the force partials, and the per-k energy and virial
-  // terms over k: each thread a contiguous run, then a tree (fixed order)
-  const int nr = sd.kchunks * sd.mtiles;
-  const int per = (nr + 255) / 256;
-  double d = 0.0;
-  {
-    const int t1 = min(nr, (tid + 1) * per);
-    int t = tid * per;
-    for (; t + 4 <= t1; t += 4) {            // four loads before their additions, same order
-      const double x0 = sd.kred[t], x1 = sd.kred[t + 1], x2 = sd.kred[t + 2], x3 = sd.kred[t + 3];
-      d += x0;
-      d += x1;
-      d += x2;
-      d += x3;
-    }
-    for (; t < t1; ++t) d += sd.kred[t];
-  }
-  const int perk = (sd.nk + 255) / 256;
-  double u = 0.0, w = 0.0;
-  for (int k = tid * perk; k < min(sd.nk, (tid + 1) * perk); ++k) {
-    u += sd.sk_part[2 * k];
-    w += sd.sk_part[2 * k + 1];
-  }
-  s_d[tid] = d;
-  s_u[tid] = u;
-  s_w[tid] = w;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-      s_d[tid] += s_d[tid + h];
-      s_u[tid] += s_u[tid + h];
-      s_w[tid] += s_w[tid + h];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double pre = 2.0 * P.ke * kTwoPi / P.V;  // 2 pi k_e / V, doubled for the half space
-    const double u_recip = pre * s_u[0], w_atomic = pre * s_w[0];
-    sd.ksum[0] = u_recip;
-    sd.ksum[1] = w_atomic;
-    const double w_mol = w_atomic - s_d[0];  // molecular virial: W_atomic - sum d.F
-    sd.sums[MS2_SUM_U_RECIP] += u_recip;
-    sd.sums[MS2_SUM_VIRIAL] += w_mol;
-    sd.sums[MS2_SUM_US] -= w_mol;
-  }
+  kspace_sums_block(sd, P, s_d, s_u, s_w);
 }
 
-hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
-                         int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
-                         int max_kchunks, hipStream_t st) {
+// The structure factor and the reciprocal force partials: everything but
+// the two reductions, which reduce_pair_kernel can take over in the MD step.
+hipError_t launch_kspace_partials(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
+                                  int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
+                                  int max_kchunks, hipStream_t st) {
   hipLaunchKernelGGL(sk_kernel, dim3(max_kblocks, max_mchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
   hipLaunchKernelGGL(sk_reduce_kernel, dim3(max_kblocks, nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_kspace(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
+                         int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
+                         int max_kchunks, hipStream_t st) {
+  const hipError_t e = launch_kspace_partials(slots, prm, tab, nslots, max_kblocks, max_mchunks, max_mtiles,
+                                              max_kchunks, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_kforce_kernel, dim3(6 * ((kMolTile * max_mtiles + 255) / 256), nslots), dim3(256),
                      0, st, slots, prm);
   hipLaunchKernelGGL(reduce_ksums_kernel, dim3(nslots), dim3(256), 0, st, slots, prm);
