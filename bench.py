@@ -303,7 +303,10 @@ CASES = {
     "lone_2cljq_2000": lambda I: I.quadrupolar_fluid(n=2000, density=0.6),
     "lone_2cljq_4000": lambda I: I.quadrupolar_fluid(n=4000, density=0.6),
     "lone_2cljq_8192": lambda I: I.quadrupolar_fluid(n=8192, density=0.6),
+    "lone_ionic_500": lambda I: I.ionic_solution(n_water=450, n_pairs=25),
     "lone_ionic_1000": lambda I: I.ionic_solution(),
+    "lone_ionic_2000": lambda I: I.ionic_solution(n_water=1800, n_pairs=100),
+    "lone_lj_1000": lambda I: I.lj_fluid(n=1000),
 }
 
 

@@ -314,14 +314,24 @@ int size_bucket(int n) {
   return b;  // floor(log2 n)
 }
 
-TileCfg default_sym_shape(int n, int cus) {
+TileCfg default_sym_shape(int n, int target) {
   const int nt = (n + 63) / 64, items = nt * (nt + 1) / 2;
   int S = 1;
-  while (S < kMaxSplits && items * S < cus) S *= 2;
+  while (S < kMaxSplits && items * S < target) S *= 2;
   TileCfg c;
   c.waves = 0;
   c.jchunk = 64 / S;
   return c;
+}
+
+TileCfg default_shape(const ms2_ctx* ctx, int n) {
+  // one item per CU for the light pair classes (LJ, 2CLJQ, Stockmayer); four
+  // for classes with charges or off-centre multipoles, whose longer pair
+  // evaluations leave the per-item work a smaller share (water + ions, lone
+  // step, S = 1 / 2 / 4: N = 500: 106 / 88 / 79 us; N = 1000: 127 / 103 / 98;
+  // N = 2000: 156 / 139 / 147)
+  const bool heavy = ctx->cls == 2 || ctx->cls >= 4;
+  return default_sym_shape(n, ctx->cus * (heavy ? 4 : 1));
 }
 
 TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
@@ -332,11 +342,12 @@ TileCfg tile_config(const ms2_ctx* ctx, int mode, int precision, int n) {
   // items from N = 500 to 8192 for the LJ, 2CLJQ and ionic models); small
   // systems deal each tile pair to 2 or 4 items so that they fill the
   // device (a lone 2CLJQ system, N = 256 / 1000: 42 -> 36 / 50 -> 43 us per
-  // MD step; water + ions, N = 1000: 134 -> 112 us).  The shape depends on n
-  // alone, so a system gets the same items alone and in a mix.
+  // MD step; water + ions, N = 1000: 127 -> 98 us).  The shape depends on the
+  // context's model class and n alone, so a system gets the same items alone
+  // and in a mix.
   (void)mode;
   (void)precision;
-  return default_sym_shape(n, ctx->cus);
+  return default_shape(ctx, n);
 }
 
 static bool single_species_form(const ms2_ctx* ctx) {

@@ -25,10 +25,11 @@ struct TileCfg {
 };
 // items per symmetric tile pair (1, 2 or 4); 1 for row-owned shapes
 inline int sym_splits(const TileCfg& c) { return c.waves == 0 && c.jchunk > 0 ? 64 / c.jchunk : 1; }
-// the untuned symmetric shape for n molecules on a device of `cus` compute
-// units: the fewest items per tile pair (1, 2, 4) that give the system at
-// least one item per compute unit
-TileCfg default_sym_shape(int n, int cus);
+// the untuned symmetric shape for n molecules: the fewest items per tile
+// pair (1, 2, 4) that give the system at least `target` items
+TileCfg default_sym_shape(int n, int target);
+// the untuned shape of a context for n molecules (symmetric items)
+TileCfg default_shape(const ms2_ctx* ctx, int n);
 
 struct CachedItems {
   DevBuf buf;

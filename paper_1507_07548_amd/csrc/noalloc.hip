@@ -148,7 +148,7 @@ extern "C" ms2_status ms2_forces_noalloc(ms2_ctx* ctx, const ms2_params* h_param
   const int n = n_mol, npad = (n + 63) & ~63, nt = npad / 64;
   // the default symmetric shape of ms2_forces (S items per tile pair), within
   // the scratch's item and partial capacity
-  int S = sym_splits(default_sym_shape(n, ctx->cus));
+  int S = sym_splits(default_shape(ctx, n));
   while (S > 1 && ((size_t)nt * (nt + 1) / 2 * S > (size_t)kNaItems || nt * S > kNaTiles)) S /= 2;
   const int nitems = nt * (nt + 1) / 2 * S;
   const int nk = h_params->elec == MS2_ELEC_EWALD ? kvec_count(h_params->kmax2) : 0;
