@@ -37,7 +37,7 @@ __device__ __forceinline__ void phase(double t, double& c, double& s) {
   sincospi(2.0 * t, &s, &c);
 }
 
-// Partial S(k) of one tile of kMolTile = 16 molecules for 64 k vectors.  A
+// Partial S(k) of one tile of kMolTile = 16 molecules for kSkK k vectors.  A
 // block is one wave; lane l owns charge l mod 4 of molecule l / 4 of the
 // tile (every model class has at most four charges per molecule) and carries
 // its phase exp(2 pi i n.r / L) from k to k: inside a line of the k set
@@ -48,6 +48,12 @@ __device__ __forceinline__ void phase(double t, double& c, double& s) {
 // segment order (8 KB of LDS per block, so that ~4 waves per SIMD fit).
 constexpr int kChargeSlots = 4;
 static_assert(kMolTile * kChargeSlots == 64, "one charge slot per lane");
+// k vectors per structure-factor block (a multiple of 8, at most 64): 32
+// puts twice the waves of 64 in flight for the phase chains, at the price of
+// more line-start sincospi (water + ions, N = 1000, lone MD step: 64 / 32 /
+// 16 k: 98.0 / 93.7 / 93.3 us)
+constexpr int kSkK = 32;
+static_assert(kSkK % 8 == 0 && kSkK <= 64, "k batches of 8, one k vector per lane at most");
 
 constexpr int max_class_charges() {
   int m = 0;
@@ -61,15 +67,15 @@ __global__ __launch_bounds__(64) void sk_kernel(const SlotDev* __restrict__ slot
                                                 const SpeciesTable* __restrict__ tab) {
   __shared__ double2 s_c[8][65];        // q exp(i k.r) per (k of the batch, lane); padded rows
   __shared__ double2 s_seg[8][8];
-  __shared__ int s_n[64][3];
-  __shared__ int s_next[64];            // 1: k continues the line of the previous k
+  __shared__ int s_n[kSkK][3];
+  __shared__ int s_next[kSkK];          // 1: k continues the line of the previous k
   const SlotDev& sd = slots[blockIdx.z];
   const SysParams& P = prm[blockIdx.z];
   if (!sd.active || P.elec != MS2_ELEC_EWALD) return;
   const int mc = blockIdx.y;
-  if (mc >= sd.mchunks || (int)blockIdx.x * 64 >= sd.nk) return;
+  if (mc >= sd.mchunks || (int)blockIdx.x * kSkK >= sd.nk) return;
   const int lane = threadIdx.x, ld = sd.com_ld;
-  const int k0 = blockIdx.x * 64, nkb = min(64, sd.nk - k0);
+  const int k0 = blockIdx.x * kSkK, nkb = min(kSkK, sd.nk - k0);
   if (lane < nkb) {
     const KVec kv = sd.kvec[k0 + lane];
     s_n[lane][0] = kv.nx;
@@ -336,7 +342,8 @@ __global__ __launch_bounds__(256) void reduce_ksums_kernel(const SlotDev* __rest
 hipError_t launch_kspace_partials(const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
                                   int nslots, int max_kblocks, int max_mchunks, int max_mtiles,
                                   int max_kchunks, hipStream_t st) {
-  hipLaunchKernelGGL(sk_kernel, dim3(max_kblocks, max_mchunks, nslots), dim3(64), 0, st, slots,
+  // max_kblocks counts blocks of 64 k vectors
+  hipLaunchKernelGGL(sk_kernel, dim3(max_kblocks * (64 / kSkK), max_mchunks, nslots), dim3(64), 0, st, slots,
                      prm, tab);
   hipLaunchKernelGGL(sk_reduce_kernel, dim3(max_kblocks, nslots), dim3(256), 0, st, slots, prm);
   hipLaunchKernelGGL(kforce_kernel, dim3(max_mtiles, max_kchunks, nslots), dim3(64), 0, st, slots,
