@@ -426,7 +426,10 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
   }
   auto J = [&](int k) { return sj[k * STRIDE]; };
 
-  // Lennard-Jones site pairs
+  // Lennard-Jones site pairs; d2U/ds2 takes (u'' - u'/r) (r.R)^2 / r^2 =
+  // (168 t12 - 48 t6) (r.R / r^2)^2 per site pair and the (u'/r) R^2 part of
+  // all of them at once
+  Real lj_dur = -Real(0);
 #pragma unroll
   for (int a = 0; a < S.lj; ++a) {
     if (a >= nlj_i) break;
@@ -452,15 +455,17 @@ __device__ __forceinline__ void eval_molecule_pair(const Real* rec, const Real* 
         t12 = in ? t12 : Real(0);
       }
       const Real dur = (Real(6) * t6 - Real(12) * t12) * ir2;       // u'/r
-      const Real d2u = (Real(156) * t12 - Real(42) * t6) * ir2;     // u''
+      const Real p = rR * ir2;
       acc.ulj += t12 - t6;
-      acc.uss += (d2u - dur) * (rR * rR * ir2) + dur * R2;
+      acc.uss += (Real(168) * t12 - Real(48) * t6) * (p * p);
+      lj_dur += dur;
       const Real fx = -dur * rx, fy = -dur * ry, fz = -dur * rz;
       ai.fl[a][0] += fx; ai.fl[a][1] += fy; ai.fl[a][2] += fz;
       if constexpr (JSIDE) { aj.fl[b][0] -= fx; aj.fl[b][1] -= fy; aj.fl[b][2] -= fz; }
       acc.fx += fx; acc.fy += fy; acc.fz += fz;
     }
   }
+  acc.uss += lj_dur * R2;
   if (SITE && !elec_in) return;
   // charge-charge site pairs
   if constexpr (S.ch > 0) {
