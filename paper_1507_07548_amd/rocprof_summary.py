@@ -32,7 +32,8 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PAIR_SOURCES = ["csrc/forces.hip", "csrc/pair_math.h", "csrc/internal.h", "csrc/site_frame.h", "csrc/quat.h"]
+PAIR_SOURCES = ["csrc/forces.hip", "csrc/pair_math.h", "csrc/internal.h", "csrc/site_frame.h", "csrc/quat.h",
+                "csrc/kspace_sums.h"]
 
 
 def pair_kernel_source_hash():
