@@ -235,42 +235,35 @@ __device__ __forceinline__ void md_begin_molecule(const SlotDev& sd, const MDDev
                                                   const SpeciesTable* __restrict__ tab, int i) {
   const int np = sd.com_ld;
   if (m.integrator == MS2_GEAR) {
-    // each part of the molecule's state (translation, angular velocity,
-    // quaternion) is loaded whole before its first store (the rows of an
-    // array lie np apart, which the compiler cannot prove non-zero), and the
-    // parts follow one another so that only one is held in registers;
-    // Pascal-triangle predictor on the 5 scaled derivatives of each
-    // component; row 4 is unchanged
+    // every load of the molecule's state is issued before the first store
+    // (the rows of an array lie np apart, which the compiler cannot prove
+    // non-zero); Pascal-triangle predictor on the 5 scaled derivatives of
+    // each component; row 4 is unchanged
     const bool rotating = m.rotating;
     double* __restrict__ const r = m.r;
     double* __restrict__ const w = m.w;
     double* __restrict__ const q = m.q;
-    {
-      double R[5][3];
-      for (int d = 0; d < 5; ++d)
-        for (int c = 0; c < 3; ++c) R[d][c] = r[(d * 3 + c) * np + i];
-      gear_predict(R);
-      for (int d = 0; d < 4; ++d)
-        for (int c = 0; c < 3; ++c) r[(d * 3 + c) * np + i] = R[d][c];
-    }
-    if (rotating) {
-      __asm__ volatile("" ::: "memory");
-      double W[5][3];
-      for (int d = 0; d < 5; ++d)
+    double R[5][3], W[5][3], Q[5][4];
+    for (int d = 0; d < 5; ++d)
+      for (int c = 0; c < 3; ++c) R[d][c] = r[(d * 3 + c) * np + i];
+    if (rotating)
+      for (int d = 0; d < 5; ++d) {
         for (int c = 0; c < 3; ++c) W[d][c] = w[(d * 3 + c) * np + i];
-      gear_predict(W);
-      for (int d = 0; d < 4; ++d)
-        for (int c = 0; c < 3; ++c) w[(d * 3 + c) * np + i] = W[d][c];
-      __asm__ volatile("" ::: "memory");
-      double Q[5][4];
-      for (int d = 0; d < 5; ++d)
         for (int c = 0; c < 4; ++c) Q[d][c] = q[(d * 4 + c) * np + i];
+      }
+    gear_predict(R);
+    for (int d = 0; d < 4; ++d)
+      for (int c = 0; c < 3; ++c) r[(d * 3 + c) * np + i] = R[d][c];
+    if (rotating) {
+      gear_predict(W);
       gear_predict(Q);
       // the force evaluation uses the predicted orientation projected onto |q| = 1
       const double nq = sqrt(Q[0][0] * Q[0][0] + Q[0][1] * Q[0][1] + Q[0][2] * Q[0][2] + Q[0][3] * Q[0][3]);
       for (int c = 0; c < 4; ++c) Q[0][c] = Q[0][c] / nq;
-      for (int d = 0; d < 4; ++d)
+      for (int d = 0; d < 4; ++d) {
+        for (int c = 0; c < 3; ++c) w[(d * 3 + c) * np + i] = W[d][c];
         for (int c = 0; c < 4; ++c) q[(d * 4 + c) * np + i] = Q[d][c];
+      }
     }
   } else {
     const double h = 0.5 * m.dt / tab->sp[clamp_species(sd.species[i], tab->nsp)].mass;
@@ -349,22 +342,48 @@ __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDe
   const double ct[5] = {19.0 / 120.0, 3.0 / 4.0, 1.0, 1.0 / 2.0, 1.0 / 12.0};
   const double cr[5] = {251.0 / 720.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0};
   if (m.integrator == MS2_GEAR) {
-    // each part of the molecule's state (translation; angular velocity;
-    // quaternion) is loaded whole before its first store: the rows of one
-    // array lie np apart, a distance the compiler cannot prove non-zero, so
-    // updates in place would chain each load behind the previous store.  The
-    // parts follow one another so that only one is held in registers.
+    // the whole state of the molecule is loaded before the first store: the
+    // rows of one array lie np apart, a distance the compiler cannot prove
+    // non-zero, so updates in place would chain each load behind the
+    // previous store
     const bool rotating = m.rotating;
     const double mass = D.mass, L = P.L, invL = P.invL;
     double R[5][3], F[3], W[5][3], Q[5][4], T[3];
     for (int d = 0; d < 5; ++d)
       for (int c = 0; c < 3; ++c) R[d][c] = gr[(d * 3 + c) * np + i];
     for (int c = 0; c < 3; ++c) F[c] = gf[c * ld + i];
-    // translation first, stored before the rotation state is loaded: the
-    // two halves never hold their registers at the same time
+    if (rotating) {
+      for (int d = 0; d < 5; ++d) {
+        for (int c = 0; c < 3; ++c) W[d][c] = gw[(d * 3 + c) * np + i];
+        for (int c = 0; c < 4; ++c) Q[d][c] = gq[(d * 4 + c) * np + i];
+      }
+      for (int c = 0; c < 3; ++c) T[c] = gt[c * ld + i];
+    }
     for (int c = 0; c < 3; ++c) {
       const double delta = 0.5 * dt * dt * F[c] / mass - R[2][c];
       for (int d = 0; d < 5; ++d) R[d][c] += ct[d] * delta;
+    }
+    if (rotating) {
+      double wd[3], qd[4], tb[3], A[3][3];
+      quat_matrix(Q[0][0], Q[0][1], Q[0][2], Q[0][3], A);
+      body_torque(A, T, tb);
+      euler_rate(D.inertia, tb, W[0], wd);
+      quat_rate(Q[0], W[0], qd);
+      for (int c = 0; c < 3; ++c) {
+        const double delta = dt * wd[c] - W[1][c];
+        for (int d = 0; d < 5; ++d) W[d][c] = W[d][c] + cr[d] * delta;
+        wo[c] = W[0][c];
+      }
+      for (int c = 0; c < 4; ++c) {
+        const double delta = dt * qd[c] - Q[1][c];
+        for (int d = 0; d < 5; ++d) Q[d][c] += cr[d] * delta;
+      }
+      const double nq = sqrt(Q[0][0] * Q[0][0] + Q[0][1] * Q[0][1] + Q[0][2] * Q[0][2] + Q[0][3] * Q[0][3]);
+      for (int c = 0; c < 4; ++c) Q[0][c] = Q[0][c] / nq;
+      for (int d = 0; d < 5; ++d) {
+        for (int c = 0; c < 3; ++c) gw[(d * 3 + c) * np + i] = W[d][c];
+        for (int c = 0; c < 4; ++c) gq[(d * 4 + c) * np + i] = Q[d][c];
+      }
     }
     for (int c = 0; c < 3; ++c) {
       R[0][c] = wrap(R[0][c], L, invL);
@@ -373,40 +392,6 @@ __device__ __forceinline__ void correct_molecule(const MDDev& m, const SpeciesDe
     for (int d = 0; d < 5; ++d)
       for (int c = 0; c < 3; ++c) gr[(d * 3 + c) * np + i] = R[d][c];
     for (int c = 0; c < 3; ++c) gv[c * np + i] = vo[c];
-    __asm__ volatile("" ::: "memory");
-    if (rotating) {
-      // angular velocity: its rates from the current orientation and torque
-      // (the quaternion rate too, from the uncorrected w), then its corrector
-      double wd[3], qd[4], tb[3], A[3][3], q0[4];
-      for (int c = 0; c < 4; ++c) q0[c] = gq[c * np + i];
-      for (int d = 0; d < 5; ++d)
-        for (int c = 0; c < 3; ++c) W[d][c] = gw[(d * 3 + c) * np + i];
-      for (int c = 0; c < 3; ++c) T[c] = gt[c * ld + i];
-      quat_matrix(q0[0], q0[1], q0[2], q0[3], A);
-      body_torque(A, T, tb);
-      euler_rate(D.inertia, tb, W[0], wd);
-      quat_rate(q0, W[0], qd);
-      for (int c = 0; c < 3; ++c) {
-        const double delta = dt * wd[c] - W[1][c];
-        for (int d = 0; d < 5; ++d) W[d][c] = W[d][c] + cr[d] * delta;
-        wo[c] = W[0][c];
-      }
-      for (int d = 0; d < 5; ++d)
-        for (int c = 0; c < 3; ++c) gw[(d * 3 + c) * np + i] = W[d][c];
-      __asm__ volatile("" ::: "memory");
-      // quaternion corrector
-      for (int c = 0; c < 4; ++c) Q[0][c] = q0[c];
-      for (int d = 1; d < 5; ++d)
-        for (int c = 0; c < 4; ++c) Q[d][c] = gq[(d * 4 + c) * np + i];
-      for (int c = 0; c < 4; ++c) {
-        const double delta = dt * qd[c] - Q[1][c];
-        for (int d = 0; d < 5; ++d) Q[d][c] += cr[d] * delta;
-      }
-      const double nq = sqrt(Q[0][0] * Q[0][0] + Q[0][1] * Q[0][1] + Q[0][2] * Q[0][2] + Q[0][3] * Q[0][3]);
-      for (int c = 0; c < 4; ++c) Q[0][c] = Q[0][c] / nq;
-      for (int d = 0; d < 5; ++d)
-        for (int c = 0; c < 4; ++c) gq[(d * 4 + c) * np + i] = Q[d][c];
-    }
   } else {
     const double h = 0.5 * dt / D.mass;
     for (int c = 0; c < 3; ++c) {
