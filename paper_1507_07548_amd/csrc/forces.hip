@@ -317,17 +317,19 @@ struct SymFinal {
 // Waves per SIMD the register allocation must allow: six for the FP32
 // two-centre quadrupole kernel of the centre cut-off (it fits 80 registers
 // without spilling, and the kernel hides its LDS latency better with six
-// waves than with five); the compiler's choice otherwise.
+// waves than with five); in FP64 four for the general single-species form
+// and three for the linear form (150 VGPRs, no spills); the compiler's
+// choice otherwise.
 template <typename Real, int C, bool HF, bool SITE, bool LIN>
 constexpr int kSymOccupancy = (sizeof(Real) == 4 && C == 1 && !HF && !SITE) ? 6
-                              : (sizeof(Real) == 8 && C == 1 && !HF && !SITE) ? 4
+                              : (sizeof(Real) == 8 && C == 1 && !HF && !SITE) ? (LIN ? 3 : 4)
                                                                              : 1;
 
 // ONE: every molecule of the system is species 0, a species with at least
 // one site of every kind its class holds (instantiated for classes 0-3); the
 // species reads and table indexing drop out, and the first site pair of each
 // kind starts its sums.
-// LIN (class 1, ONE, centre cut-off, no heat flux, FP32): the species is a
+// LIN (class 1, ONE, centre cut-off, no heat flux): the species is a
 // linear two-centre LJ + quadrupole molecule (eval_linear_pair); only the
 // first LJ site's offset and the quadrupole axis of each molecule are staged
 // (278 instead of 319 VALU instructions in the pair loop; 4.37 -> 4.29 ms on
@@ -339,7 +341,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   const SlotDev* __restrict__ slots,
                                                                   const SysParams* __restrict__ prm,
                                                                   const SpeciesTable* __restrict__ tab) {
-  static_assert(!LIN || (C == 1 && ONE && !HF && !SITE && sizeof(Real) == 4),
+  static_assert(!LIN || (C == 1 && ONE && !HF && !SITE),
                 "the linear form is a class-1 single-species FP32 form");
   // reals of the site record staged per molecule: all of them, or (LIN) the
   // first LJ site's offset (the record's first three) and the quadrupole
@@ -887,9 +889,10 @@ template <typename Real, int C, bool HF, bool SITE>
 static hipError_t launch_pair_sym(int form, const WorkItem* items, int base, int count,
                                   const SlotDev* slots, const SysParams* prm, const SpeciesTable* tab,
                                   hipStream_t st) {
-  // the linear form in FP32 only: in FP64 its 4-wave register budget spills
-  // (13.7 against 8.0 ms per step of the batched workload, measured)
-  if constexpr (C == 1 && !HF && !SITE && sizeof(Real) == 4) {
+  // the linear form; in FP64 it runs at three waves per SIMD (150 VGPRs: at
+  // four it spills, 13.7 against 8.0 ms per batched step; at three, 8.13
+  // against 8.22 ms for the general single-species form at four)
+  if constexpr (C == 1 && !HF && !SITE) {
     if (form == kFormLinear) {
       hipLaunchKernelGGL((pair_sym_kernel<Real, C, HF, SITE, true, true>), dim3(count), dim3(64 * kSymWaves), 0,
                          st, items, base, slots, prm, tab);
