@@ -342,7 +342,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
                                                                   const SysParams* __restrict__ prm,
                                                                   const SpeciesTable* __restrict__ tab) {
   static_assert(!LIN || (C == 1 && ONE && !HF && !SITE),
-                "the linear form is a class-1 single-species FP32 form");
+                "the linear form is a class-1 single-species form of the centre cut-off");
   // reals of the site record staged per molecule: all of them, or (LIN) the
   // first LJ site's offset (the record's first three) and the quadrupole
   // axis (its last three)
