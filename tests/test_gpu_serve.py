@@ -13,7 +13,7 @@ if not torch.cuda.is_available():
     pytest.skip("no HIP device", allow_module_level=True)
 
 from paper_1507_07548_amd import ms2  # noqa: E402
-from paper_1507_07548_amd.serve import GpuBackend, Request, Server  # noqa: E402
+from paper_1507_07548_amd.serve import GpuBackend, Request, Server, backend_key  # noqa: E402
 
 
 def families():
@@ -21,14 +21,18 @@ def families():
             "ionic": [I.water_tip4p_like(), I.cation(), I.anion()]}
 
 
-def test_served_results_equal_the_same_request_run_alone():
-    trace = I.serving_trace(n_requests=9, rate=400.0, seed=7, n_lo=200, n_hi=700, n_steps=120,
+@pytest.mark.parametrize("max_inflight", [None, 2])
+def test_served_results_equal_the_same_request_run_alone(max_inflight):
+    """Batches per model family and size class; every batch launching, or two
+    at a time in shortest-remaining-work order."""
+    trace = I.serving_trace(n_requests=9, rate=400.0, seed=7, n_lo=200, n_hi=1500, n_steps=120,
                             window=60, acf_every=6, origin_every=30)
-    print("[gpu] serving", [(round(t, 3), m, s.n) for t, m, s in trace], flush=True)
+    print(f"[gpu] serving max_inflight={max_inflight}", [(round(t, 3), m, s.n) for t, m, s in trace], flush=True)
     fam = families()
-    backends = {m: GpuBackend(fam[m], max_slots=3) for m in fam}
-    reqs = [Request(r, t, m, s, ms2.FP32) for r, (t, m, s) in enumerate(trace)]
-    srv = Server(backends, hbm_budget=1 << 34, chunk_steps=40)
+    keys = sorted({backend_key(m, s.n) for _, m, s in trace})
+    backends = {k: GpuBackend(fam[k.split("/")[0]], max_slots=3) for k in keys}
+    reqs = [Request(r, t, backend_key(m, s.n), s, ms2.FP32) for r, (t, m, s) in enumerate(trace)]
+    srv = Server(backends, hbm_budget=1 << 34, chunk_steps=40, max_inflight=max_inflight)
     res = {r.rid: r for r in srv.run(reqs)}
     assert sorted(res) == list(range(len(reqs)))
     # some request was admitted while another one was already running
@@ -37,7 +41,7 @@ def test_served_results_equal_the_same_request_run_alone():
     for r in reqs:
         got = res[r.rid]
         assert got.status == 0 and got.steps_done == r.system.md.n_steps
-        ctx = ms2.Context(fam[r.model])
+        ctx = ms2.Context(fam[r.model.split("/")[0]])
         alone = ms2.Batch(ctx, 1)
         slot = alone.admit(r.system, ms2.FP32)
         alone.step(r.system.md.n_steps)
