@@ -348,6 +348,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   // axis (its last three)
   constexpr int NR = LIN ? 6 : class_reals(C);
   constexpr int TJ = 64, NW = kSymWaves;
+  static_assert(NW == 4 || NW == 8, "waves 0-3 stage the tiles and write the partials");
 
   constexpr int NL64 = SITE ? 3 * kClassShapes[C].lj : 0;
   __shared__ union {
@@ -388,7 +389,9 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     const int side = wv & 1;
     const int base = side ? it.j0 : it.i0, cnt = side ? ncol : nrow;
     const int mc = lane < cnt ? base + lane : 0;
-    if (wv < 2) {
+    if (wv >= 4) {
+      // further waves stage nothing
+    } else if (wv < 2) {
       double c3[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) c3[c] = sd.com[c * ld + mc];
@@ -430,25 +433,27 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   }
   __syncthreads();
 
-  // 1. cut-off bits: wave wv tests columns [16 wv, 16 wv + 16) of row `lane`
+  // 1. cut-off bits: wave wv tests columns [CW wv, CW wv + CW) of row `lane`
   //    (centres in [0, L], the usual case: the image-free form of the same r2)
+  constexpr int CW = TJ / NW;               // columns (and diagonals) per wave
+  constexpr unsigned kWaveBits = CW >= 32 ? 0xFFFFFFFFu : (1u << CW) - 1u;
   {
     const double xi = u.t.comi[0][lane], yi = u.t.comi[1][lane], zi = u.t.comi[2][lane];
     const bool inbox = __builtin_amdgcn_readfirstlane(s_inbox[0] & s_inbox[1]) != 0;
-    // the columns this row may pair with, as bits of the wave's 16: inside
+    // the columns this row may pair with, as bits of the wave's CW: inside
     // the tile, and on the diagonal item above the row
-    const int j0 = 16 * wv, nv = ncol - j0, s = lane - j0 + 1;
-    unsigned valid = nv >= 16 ? 0xFFFFu : nv > 0 ? (1u << nv) - 1u : 0u;
-    if (diag) valid &= s <= 0 ? 0xFFFFu : s < 16 ? (0xFFFFu << s) & 0xFFFFu : 0u;
+    const int j0 = CW * wv, nv = ncol - j0, s = lane - j0 + 1;
+    unsigned valid = nv >= CW ? kWaveBits : nv > 0 ? (1u << nv) - 1u : 0u;
+    if (diag) valid &= s <= 0 ? kWaveBits : s < CW ? (kWaveBits << s) & kWaveBits : 0u;
     const double* cj = &u.t.comj[0][j0];
     unsigned part = 0;
     if (inbox) {
-      for (int b = 0; b < 16; ++b) {
+      for (int b = 0; b < CW; ++b) {
         const double r2 = min_image_r2(xi, yi, zi, cj[b], cj[TJ + b], cj[2 * TJ + b], L);
         part |= (unsigned)(r2 < rlist2) << b;
       }
     } else {
-      for (int b = 0; b < 16; ++b) {
+      for (int b = 0; b < CW; ++b) {
         double dx, dy, dz, r2;
         min_image(xi, yi, zi, cj[b], cj[TJ + b], cj[2 * TJ + b], L, invL, dx, dy, dz, r2);
         part |= (unsigned)(r2 < rlist2) << b;
@@ -458,18 +463,18 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   }
   __syncthreads();
   // row masks rotated so that bit d is column lane + d; wave wv transposes
-  // diagonals [16 wv, 16 wv + 16)
+  // diagonals [CW wv, CW wv + CW)
   {
     unsigned long long m = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) m |= (unsigned long long)s_mpart[w][lane] << (16 * w);
+    for (int w = 0; w < NW; ++w) m |= (unsigned long long)s_mpart[w][lane] << (CW * w);
     m = lane == 0 ? m : ((m >> lane) | (m << (TJ - lane)));
-    // this wave's 16 diagonals lie in one 32-bit half of m
-    const unsigned half = wv < 2 ? (unsigned)m : (unsigned)(m >> 32);
-    const int sh = 16 * (wv & 1);
-    for (int b = 0; b < 16; ++b) {
+    // this wave's CW diagonals lie in one 32-bit half of m
+    const unsigned half = CW * wv < 32 ? (unsigned)m : (unsigned)(m >> 32);
+    const int sh = (CW * wv) & 31;
+    for (int b = 0; b < CW; ++b) {
       const unsigned long long w = __builtin_amdgcn_ballot_w64(((half >> (sh + b)) & 1u) != 0u);
-      if (lane == 0) s_dw[16 * wv + b] = w;
+      if (lane == 0) s_dw[CW * wv + b] = w;
     }
   }
   __syncthreads();
@@ -626,7 +631,7 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   // wave w writes three of the twelve components (rows 0-2, rows 3-5,
   // columns 0-2, columns 3-5), each summed over the waves in wave order; on
   // the diagonal item the columns are the rows and waves 0/1 add both
-  {
+  if (wv < 4) {
     const bool col_side = wv >= 2;
     const int c0 = 3 * (wv & 1);
     Real* pf = reinterpret_cast<Real*>(sd.pf);
