@@ -227,9 +227,10 @@ __global__ __launch_bounds__(64 * W) void pair_kernel(const WorkItem* __restrict
 //  1. the cut-off bits of the 64 x 64 pairs (FP64, j > i on the diagonal
 //     tile; each wave tests 16 columns of every row) are rotated right by
 //     the row index l, so that bit d marks pair (l, l + d): "diagonal" d of
-//     the tile.  Ballots transpose the rows into one 64-bit word per
-//     diagonal (each wave 16 of them); a wave scan of their counts gives
-//     each diagonal's offset in the diagonal-major list of accepted pairs.
+//     the tile.  Every wave transposes the 64 x 64 bits in registers (lane
+//     swizzles, no shared memory, no barrier), so that lane d holds diagonal
+//     d's 64-bit word; a wave scan of their counts gives each diagonal's
+//     offset in the diagonal-major list of accepted pairs.
 //  2. the list is processed 64 entries at a time, one pair per lane, the
 //     chunks dealt to the waves in turn.  A chunk's diagonals follow from
 //     two ballots over the offsets.  For each of them lane m holds row m's
@@ -288,11 +289,59 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, i
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Orders this wave's LDS accesses before and after (the wave's lanes only).
+// One stage of the wave's 64 x 64 bit transpose (wave_bit_transpose): lane-
+// index bit S trades places with bit-position bit S inside each 32-bit half.
+// Lane l keeps its bits whose position agrees with l in bit S and takes the
+// others from lane l ^ S (an LDS swizzle, no VALU), rotated by S the way
+// that lands them in place: left where l has bit S clear, right where set.
+template <int S>
+__device__ __forceinline__ void bit_transpose_stage(unsigned& lo, unsigned& hi) {
+  constexpr unsigned kLow = S == 16 ? 0x0000FFFFu : S == 8 ? 0x00FF00FFu : S == 4 ? 0x0F0F0F0Fu
+                            : S == 2 ? 0x33333333u : 0x55555555u;   // positions with bit S clear
+  constexpr unsigned long long kUp = S == 16 ? 0xFFFF0000FFFF0000ull : S == 8 ? 0xFF00FF00FF00FF00ull
+                                     : S == 4 ? 0xF0F0F0F0F0F0F0F0ull : S == 2 ? 0xCCCCCCCCCCCCCCCCull
+                                                                      : 0xAAAAAAAAAAAAAAAAull;   // lanes with bit S set
+  constexpr int kXor = 0x1F | (S << 10);   // swizzle, bit-mask mode: lane (l & 31) ^ S of its half
+  const bool up = __builtin_amdgcn_inverse_ballot_w64(kUp);
+  const unsigned keep = kLow ^ (up ? ~0u : 0u);
+  const unsigned amt = up ? S : 32 - S;
+  const unsigned plo = (unsigned)__builtin_amdgcn_ds_swizzle((int)lo, kXor);
+  const unsigned phi = (unsigned)__builtin_amdgcn_ds_swizzle((int)hi, kXor);
+  lo = (lo & keep) | (__builtin_amdgcn_alignbit(plo, plo, amt) & ~keep);
+  hi = (hi & keep) | (__builtin_amdgcn_alignbit(phi, phi, amt) & ~keep);
+}
+
+// 64 x 64 bit-matrix transpose held one row per lane: lane l passes word r
+// (bit c: element (l, c)) and gets back the word whose bit c is element
+// (c, l).  The six stages (lane-index bit s against bit-position bit s, s =
+// 32, 16, ..., 1) commute; for s = 32 the 32-bit halves cross between lanes
+// l and l ^ 32.  Registers and LDS swizzles only: no shared memory, no
+// barrier.
+__device__ __forceinline__ unsigned long long wave_bit_transpose(unsigned long long r) {
+  unsigned lo = (unsigned)r, hi = (unsigned)(r >> 32);
+  {
+    const int lane = threadIdx.x & 63;
+    const bool up = __builtin_amdgcn_inverse_ballot_w64(0xFFFFFFFF00000000ull);
+    const unsigned recv = (unsigned)__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(up ? lo : hi));
+    lo = up ? recv : lo;
+    hi = up ? hi : recv;
+  }
+  bit_transpose_stage<16>(lo, hi);
+  bit_transpose_stage<8>(lo, hi);
+  bit_transpose_stage<4>(lo, hi);
+  bit_transpose_stage<2>(lo, hi);
+  bit_transpose_stage<1>(lo, hi);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Orders this wave's LDS accesses before and after, for the wave's own
+// lanes only: a wave's LDS operations are performed in issue order, so
+// fences of wavefront scope suffice and cost no wait (workgroup scope would
+// drain the wave's outstanding LDS operations at each call).
 __device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename Real, int NR, bool HF, int NL64>
@@ -358,7 +407,6 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
   __shared__ int s_sp[ONE ? 1 : 2][ONE ? 1 : TJ];   // species of rows, columns (not read when ONE)
   __shared__ PairTables<Real, C, ONE ? 1 : kMaxSp> s_tab;
   __shared__ unsigned s_mpart[NW][TJ];
-  __shared__ unsigned long long s_dw[TJ];
   __shared__ int s_list[NW][TJ];          // per wave: row | diagonal << 6 of each entry of the chunk
   __shared__ int s_inbox[2];              // 1: every staged centre of the side lies in [0, L]
 
@@ -462,23 +510,24 @@ void pair_sym_kernel(const WorkItem* __restrict__ items,
     s_mpart[wv][lane] = lane < nrow ? part & valid : 0u;
   }
   __syncthreads();
-  // row masks rotated so that bit d is column lane + d; wave wv transposes
-  // diagonals [CW wv, CW wv + CW)
+  // every wave: the row mask rotated so that bit d is column lane + d, then
+  // transposed, so that lane d holds diagonal d's word (bit l: the pair (l,
+  // l + d)) of every row l
+  unsigned long long dword;
   {
-    unsigned long long m = 0;
+    unsigned m0 = 0, m1 = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) m |= (unsigned long long)s_mpart[w][lane] << (CW * w);
-    m = lane == 0 ? m : ((m >> lane) | (m << (TJ - lane)));
-    // this wave's CW diagonals lie in one 32-bit half of m
-    const unsigned half = CW * wv < 32 ? (unsigned)m : (unsigned)(m >> 32);
-    const int sh = (CW * wv) & 31;
-    for (int b = 0; b < CW; ++b) {
-      const unsigned long long w = __builtin_amdgcn_ballot_w64(((half >> (sh + b)) & 1u) != 0u);
-      if (lane == 0) s_dw[CW * wv + b] = w;
+    for (int w = 0; w < NW; ++w) {
+      if (CW * w < 32) m0 |= s_mpart[w][lane] << (CW * w);
+      else m1 |= s_mpart[w][lane] << (CW * w - 32);
     }
+    // rotate right by lane: halves swapped for lanes 32-63, then a funnel
+    // shift by lane & 31
+    const bool swap = lane >= 32;
+    const unsigned a = swap ? m1 : m0, b = swap ? m0 : m1;
+    const unsigned lo = __builtin_amdgcn_alignbit(b, a, lane & 31), hi = __builtin_amdgcn_alignbit(a, b, lane & 31);
+    dword = wave_bit_transpose(((unsigned long long)hi << 32) | lo);
   }
-  __syncthreads();
-  const unsigned long long dword = s_dw[lane];   // lane d: the pairs (l, l + d) of every row l
   const int cnt = __popcll(dword);
   const int incl = wave_inclusive_sum(cnt);
   const int doff = incl - cnt;               // lane d: offset of diagonal d
